@@ -1,0 +1,149 @@
+"""NRTO-DR: the inner ADMM of NRTO with its {k_v, p~} block solved by relaxed
+Douglas-Rachford splitting (Section III; supplementary section II).
+
+ADMM (the three updates of Section II-B; the dual update uses the current
+p - p~, a reading of the printed superscripts):
+    {k_v, p~} <- DR solve of the subproblem (eq. dr-subproblem)
+    {du, p}   <- oracle.qp with c = p~ - lambda / rho
+    lambda    <- lambda + rho (p - p~)
+
+DR on min 1/2 chi'P chi + q'chi s.t. A chi + s = b, s in K, chi = [k_v; p~],
+P = blkdiag(Q_v, rho I), q = [0; -(rho p + lambda)], s_j = (t_j, eta_j),
+t_j = p~_j, eta_j = A_hat_j k_v + b_hat_j (supplementary II-A):
+    xi       = Prox_J(xi~)                 affine-set prox, R_chi = sigma_chi I,
+                                           R_s = sigma_s I; y eliminated, so the
+                                           k_v block is solved with
+                                           H = Q_v + sigma_chi I + sigma_s sum_j A_hat_j'A_hat_j
+                                           (dense Cholesky, factored once) and
+                                           s = b - A chi
+    xi_ref   = 2 xi - xi~
+    xi~     += alpha (Prox_Jhat(xi_ref) - xi),  Prox_Jhat = (identity on chi, Pi_K on s)
+stopped when ||s~_new - s~_old||_2 <= eps_abs + eps_rel max(1, ||s~||) or after
+max_dr steps.  The DR state xi~ is carried from one ADMM iteration to the next.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Callable, Optional
+
+import numpy as np
+import scipy.linalg as sla
+
+from . import kkt, qp
+from .linearize import AtA_dense, K_to_kv, Qv_dense, eta, eta_adjoint, kv_to_K
+from .soc import project_rows_vec
+
+
+@dataclasses.dataclass
+class Options:
+    rho: float = 40.0
+    alpha: float = 1.0
+    sigma_chi: float = 1.0
+    sigma_s: float = 1.0
+    eps_dr_abs: float = 1e-4
+    eps_dr_rel: float = 1e-4
+    max_dr: int = 100
+    max_admm: int = 40
+    eps_kkt: float = 1e-4
+    check_every: int = 1
+    eps_p: float = 0.0
+    eps_d: float = 0.0
+
+
+@dataclasses.dataclass
+class State:
+    K_t: np.ndarray      # K~   (T, nu, nx)
+    pt_t: np.ndarray     # p~~  (ng,)
+    s_t: np.ndarray      # s~   (ng, 1 + nz): column 0 = t, then eta
+    du: np.ndarray
+    p: np.ndarray
+    lam: np.ndarray
+    K: np.ndarray        # last chi (k_v part)
+    pt: np.ndarray       # last chi (p~ part)
+    pi: np.ndarray
+    mu: float
+
+
+def zero_state(socp) -> State:
+    T, nu, nx, ng = socp.T, socp.nu, socp.nx, socp.ng
+    return State(K_t=np.zeros((T, nu, nx)), pt_t=np.zeros(ng), s_t=np.zeros((ng, 1 + socp.nz)),
+                 du=np.zeros(T * nu), p=np.zeros(ng), lam=np.zeros(ng),
+                 K=np.zeros((T, nu, nx)), pt=np.zeros(ng), pi=np.zeros(ng), mu=0.0)
+
+
+def zeta(socp, opt: Options, st: State) -> np.ndarray:
+    """Cone multiplier y_eta = sigma_s (eta~ - eta(K)) of the affine-set prox."""
+    return opt.sigma_s * (st.s_t[:, 1:] - eta(socp, st.K))
+
+
+def residual(socp, opt: Options, st: State) -> float:
+    return kkt.residual(socp, st.du, st.K, st.p, st.pt, st.pi, st.mu, zeta(socp, opt, st))
+
+
+def factor(socp, opt: Options):
+    n = socp.T * socp.nu * socp.nx
+    Hk = Qv_dense(socp) + opt.sigma_chi * np.eye(n) + opt.sigma_s * AtA_dense(socp)
+    return sla.cho_factor(Hk, lower=True)
+
+
+def dr_steps(socp, opt: Options, st: State, fac, max_steps: int, trace: Optional[Callable] = None):
+    """Run up to max_steps relaxed DR iterations on the current subproblem; returns (steps, r_dr)."""
+    rho, al, sx, ss = opt.rho, opt.alpha, opt.sigma_chi, opt.sigma_s
+    T, nu, nx = socp.T, socp.nu, socp.nx
+    r_dr = np.inf
+    it = 0
+    for it in range(1, max_steps + 1):
+        # Prox_J: reduced KKT solve
+        R = sx * st.K_t + ss * eta_adjoint(socp, st.s_t[:, 1:] - socp.bhat)
+        K = kv_to_K(sla.cho_solve(fac, K_to_kv(R)), T, nu, nx)
+        pt = (sx * st.pt_t + rho * st.p + st.lam + ss * st.s_t[:, 0]) / (rho + sx + ss)
+        S = np.empty_like(st.s_t)
+        S[:, 0] = pt
+        S[:, 1:] = eta(socp, K)
+        # reflection, cone prox, relaxation
+        S_ref = 2.0 * S - st.s_t
+        S_hat = project_rows_vec(S_ref)
+        st.K_t = st.K_t + al * (K - st.K_t)
+        st.pt_t = st.pt_t + al * (pt - st.pt_t)
+        dS = al * (S_hat - S)
+        st.s_t = st.s_t + dS
+        st.K, st.pt = K, pt
+        r_dr = float(np.sqrt(np.sum(dS * dS)))
+        if trace is not None:
+            trace("dr", it, st)
+        if r_dr <= opt.eps_dr_abs + opt.eps_dr_rel * max(1.0, float(np.sqrt(np.sum(st.s_t * st.s_t)))):
+            break
+    return it, r_dr
+
+
+def solve(socp, opt: Options = Options(), st: Optional[State] = None, trace: Optional[Callable] = None):
+    """Returns (State, info dict)."""
+    if st is None:
+        st = zero_state(socp)
+    fac = factor(socp, opt)
+    info = {"admm_iters": 0, "dr_iters": 0, "kkt": np.inf, "status": "maxiter", "r_p": np.inf, "r_d": np.inf}
+    pt_prev = st.pt.copy()
+    for l in range(1, opt.max_admm + 1):
+        n_dr, _ = dr_steps(socp, opt, st, fac, opt.max_dr, trace)
+        info["dr_iters"] += n_dr
+        c = st.pt - st.lam / opt.rho
+        st.du, st.p, st.pi, st.mu = qp.solve(socp.H, socp.h, socp.bmat, socp.g0, c, opt.rho,
+                                             socp.Fu, socp.r_trust, st.du)
+        st.lam = st.lam + opt.rho * (st.p - st.pt)
+        info["admm_iters"] = l
+        info["r_p"] = float(np.linalg.norm(st.p - st.pt))
+        info["r_d"] = float(opt.rho * np.linalg.norm(st.pt - pt_prev))
+        pt_prev = st.pt.copy()
+        if trace is not None:
+            trace("admm", l, st)
+        stop = False
+        if opt.eps_kkt > 0 and (l % opt.check_every == 0):
+            info["kkt"] = residual(socp, opt, st)
+            stop = info["kkt"] <= opt.eps_kkt
+        if opt.eps_p > 0 and opt.eps_d > 0 and info["r_p"] <= opt.eps_p and info["r_d"] <= opt.eps_d:
+            stop = True
+        if stop:
+            info["status"] = "ok"
+            break
+    info["kkt"] = residual(socp, opt, st)
+    return st, info

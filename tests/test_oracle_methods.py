@@ -1,0 +1,159 @@
+"""Pins of the oracle's NRTO-DR and NRTO-FullADMM:
+
+* the reduced affine-set prox equals the solution of the full quasi-definite
+  KKT system of supplementary II-B, solved densely;
+* FullADMM keeps Q_v k_v + rho sum_j A_hat_j' lambda_nu_j = 0 (supplementary
+  III) and its closed-form k_v step equals the standard ADMM k_v step;
+* both methods reach the same unique (du*, k_v*) as an independent
+  general-purpose NLP solver (SciPy SLSQP) on small problems;
+* the ball radius r = 0 gives K* = 0 and the nominal QP solution.
+"""
+import numpy as np
+import pytest
+import scipy.optimize as so
+
+import synth
+from oracle import dr, fulladmm, kkt, linearize
+from oracle.linearize import eta, eta_adjoint
+
+
+def near_obstacle_socp(T=8, radius=0.05, r_trust=5.0):
+    """Unicycle driving along x at 1 m/s past an obstacle just off its path,
+    so the robust obstacle constraints are active and K* is nonzero."""
+    prob = synth.config1()
+    prob.T = T
+    prob.radius = radius
+    prob.u_init = np.tile([1.0, 0.0], (T, 1))
+    prob.obstacles = np.array([[0.45, 0.3, 0.15]])
+    return linearize.assemble(prob, prob.u_init, r_trust)
+
+
+def dense_conic(s, rho, p, lam):
+    """P, q, A, b of the DR standard form (supplementary II-A) written out."""
+    n = s.T * s.nu * s.nx
+    ng, nz = s.ng, s.nz
+    P = np.zeros((n + ng, n + ng))
+    P[:n, :n] = linearize.Qv_dense(s)
+    P[n:, n:] = rho * np.eye(ng)
+    q = np.concatenate([np.zeros(n), -(rho * p + lam)])
+    A = np.zeros((ng * (1 + nz), n + ng))
+    b = np.zeros(ng * (1 + nz))
+    for j in range(ng):
+        r0 = j * (1 + nz)
+        A[r0, n + j] = -1.0
+        A[r0 + 1:r0 + 1 + nz, :n] = -linearize.A_hat_dense(s, j)
+        b[r0 + 1:r0 + 1 + nz] = s.bhat[j]
+    return P, q, A, b
+
+
+def test_reduced_prox_equals_full_kkt():
+    s = near_obstacle_socp(T=3)
+    o = dr.Options(rho=40.0, sigma_chi=0.7, sigma_s=1.3)
+    d = synth.Draws(21)
+    st = dr.zero_state(s)
+    st.K_t = d.u(st.K_t.size, -1, 1).reshape(st.K_t.shape)
+    st.pt_t = d.u(s.ng, -1, 1)
+    st.s_t = d.u(st.s_t.size, -1, 1).reshape(st.s_t.shape)
+    st.p = d.u(s.ng, -1, 1)
+    st.lam = d.u(s.ng, -1, 1)
+    chi_t = np.concatenate([linearize.K_to_kv(st.K_t), st.pt_t])
+    s_t = st.s_t.ravel().copy()
+    P, q, A, b = dense_conic(s, o.rho, st.p, st.lam)
+    nchi, m = P.shape[0], A.shape[0]
+    Kkkt = np.block([[P + o.sigma_chi * np.eye(nchi), A.T], [A, -np.eye(m) / o.sigma_s]])
+    rhs = np.concatenate([o.sigma_chi * chi_t - q, b - s_t])
+    sol = np.linalg.solve(Kkkt, rhs)
+    chi, y = sol[:nchi], sol[nchi:]
+    s_new = s_t - y / o.sigma_s
+    assert np.max(np.abs(Kkkt @ sol - rhs)) <= 1e-12
+    # one oracle DR step records chi = (K, p~) of its prox
+    dr.dr_steps(s, o, st, dr.factor(s, o), 1)
+    n = s.T * s.nu * s.nx
+    assert np.allclose(linearize.K_to_kv(st.K), chi[:n], atol=1e-12)
+    assert np.allclose(st.pt, chi[n:], atol=1e-12)
+    S = np.concatenate([st.pt[:, None], eta(s, st.K)], axis=1).ravel()
+    assert np.allclose(S, s_new, atol=1e-12)
+
+
+def test_fulladmm_invariant_and_standard_step():
+    s = near_obstacle_socp()
+    o = fulladmm.Options(rho=10.0, max_admm=1)
+    st = fulladmm.zero_state(s)
+    fac = fulladmm.factor(s, o)
+    for _ in range(25):
+        K_prev, lam_prev = st.K.copy(), st.lam_nu.copy()
+        fulladmm.iterate(s, o, st, fac)
+        inv = fulladmm.invariant(s, o, st)
+        assert np.max(np.abs(inv)) <= 1e-12 * (1 + np.max(np.abs(st.K)) + o.rho * np.max(np.abs(st.lam_nu)))
+        # standard step: (Q_v + rho sum A'A) k = -rho sum A'(b_hat - nu + lambda_nu_prev)
+        n = s.T * s.nu * s.nx
+        M = linearize.Qv_dense(s) + o.rho * linearize.AtA_dense(s)
+        rhs = -o.rho * linearize.K_to_kv(eta_adjoint(s, s.bhat - st.nu_ + lam_prev))
+        assert np.allclose(np.linalg.solve(M, rhs), linearize.K_to_kv(st.K), atol=1e-10)
+
+
+def _slsqp(s):
+    """Problem 2 with p eliminated, solved by SLSQP in (du, k_v)."""
+    nd = s.T * s.nu
+    nk = s.T * s.nu * s.nx
+    Qv = linearize.Qv_dense(s)
+
+    def f(z):
+        du, kv = z[:nd], z[nd:]
+        return 0.5 * du @ s.H @ du + s.h @ du + 0.5 * kv @ Qv @ kv
+
+    def cons(z):
+        du, kv = z[:nd], z[nd:]
+        E = eta(s, linearize.kv_to_K(kv, s.T, s.nu, s.nx))
+        return -(s.g0 + s.bmat @ du + np.sqrt(np.sum(E * E, axis=1) + 1e-30))
+
+    def trust(z):
+        return s.r_trust ** 2 - np.sum((s.Fu @ z[:nd]) ** 2)
+
+    z0 = np.zeros(nd + nk)
+    res = so.minimize(f, z0, method="SLSQP", constraints=[{"type": "ineq", "fun": cons},
+                                                          {"type": "ineq", "fun": trust}],
+                      options={"ftol": 1e-14, "maxiter": 2000})
+    return res.x[:nd], linearize.kv_to_K(res.x[nd:], s.T, s.nu, s.nx)
+
+
+def test_methods_agree_with_independent_solver():
+    s = near_obstacle_socp(T=6)
+    od = dr.Options(max_dr=1000, max_admm=300, eps_kkt=1e-7, eps_dr_abs=1e-9, eps_dr_rel=1e-9)
+    sd, idr = dr.solve(s, od)
+    of = fulladmm.Options(max_admm=20000, eps_kkt=1e-8)
+    sf, ifa = fulladmm.solve(s, of)
+    assert idr["kkt"] <= 1e-7 and ifa["kkt"] <= 1e-8
+    assert np.max(np.abs(sd.K)) > 1e-3          # the gains matter on this problem
+    du_ref, K_ref = _slsqp(s)
+    assert np.allclose(sd.du, sf.du, atol=2e-5)
+    assert np.allclose(sd.K, sf.K, atol=2e-5)
+    assert np.allclose(sd.du, du_ref, atol=2e-5)
+    assert np.allclose(sd.K, K_ref, atol=2e-5)
+
+
+def test_zero_radius_gives_zero_gain_and_nominal_qp():
+    s = near_obstacle_socp(T=6, radius=0.0)
+    sd, info = fulladmm.solve(s, fulladmm.Options(max_admm=20000, eps_kkt=1e-10))
+    assert np.max(np.abs(sd.K)) <= 1e-12
+    nd = s.T * s.nu
+    res = so.minimize(lambda u: 0.5 * u @ s.H @ u + s.h @ u, np.zeros(nd), method="SLSQP",
+                      constraints=[{"type": "ineq", "fun": lambda u: -(s.g0 + s.bmat @ u)},
+                                   {"type": "ineq", "fun": lambda u: s.r_trust ** 2 - np.sum((s.Fu @ u) ** 2)}],
+                      options={"ftol": 1e-15, "maxiter": 1000})
+    assert np.allclose(sd.du, res.x, atol=1e-6)
+
+
+def test_dr_fixed_point_certificate():
+    # at convergence y_hat = sigma_s (s_hat - s_ref) is in K and orthogonal to s_hat
+    s = near_obstacle_socp(T=5)
+    o = dr.Options(max_dr=4000, max_admm=1, eps_dr_abs=1e-12, eps_dr_rel=1e-12, eps_kkt=0)
+    st, _ = dr.solve(s, o)
+    S = np.concatenate([st.pt[:, None], eta(s, st.K)], axis=1)
+    S_ref = 2 * S - st.s_t
+    from oracle.soc import project_rows_vec
+    S_hat = project_rows_vec(S_ref)
+    Y = o.sigma_s * (S_hat - S_ref)
+    assert np.all(np.linalg.norm(Y[:, 1:], axis=1) <= Y[:, 0] + 1e-9)
+    assert np.max(np.abs(np.sum(Y * S_hat, axis=1))) <= 1e-9
+    assert np.max(np.abs(S_hat - S)) <= 1e-9
