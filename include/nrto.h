@@ -1,0 +1,228 @@
+/*
+ * nrto.h -- C ABI of the MI355X (gfx950) robust-SOCP inner solver.
+ *
+ * The library solves, for a batch of robust trajectory problems, the tractable
+ * linearised problem of one successive-linearisation step (cuNRTO, arXiv
+ * 2603.02642, Problem 2):
+ *
+ *   min_{du, k_v, p}  Q_u(du) + 1/2 k_v' Q_v k_v
+ *   s.t.  g0_j + b_j' du + p_j <= 0,  ||A_hat_j k_v + b_hat_j||_2 <= p_j  (j = 1..n_g),
+ *         ||F_u du||_2 <= r_trust,
+ *
+ * by NRTO-DR (inner ADMM with its {k_v, p~} block solved by relaxed
+ * Douglas-Rachford splitting, Section III and supplementary II) or by
+ * NRTO-FullADMM (Section IV, Algorithm 1, supplementary III).  Problems follow
+ * Problem 1: x_{k+1} = f(x_k, u_k) + d_k, x_0 = x0 + d0, disturbances stacked in
+ * zeta and bounded by the ball ||zeta|| <= radius (Gamma = S = I, tau = radius^2),
+ * affine policy u_k = u_bar_k + K_k zeta_k, constraints required for every zeta.
+ *
+ * Conventions (all functions):
+ *  - Every function returns an nrto_status; no C++ exception or abort crosses
+ *    the ABI.  On a non-OK status, nrto_last_error(ctx) (or nrto_last_error(NULL)
+ *    for calls without a context) returns a thread-local message.
+ *  - Host pointers are read during the call only and never retained; the
+ *    context deep-copies problem data.  Device pointers passed to
+ *    nrto_project_soc are owned by the caller and must stay valid until the
+ *    stream has executed the work.
+ *  - A context is bound to one HIP stream (the one given to nrto_setup) and is
+ *    not thread-safe.  Calls enqueue work on that stream; calls that return
+ *    results to host memory synchronise the stream.
+ *  - Arrays are row-major float64 unless stated.  Gains K_k (n_u x n_x) are
+ *    returned as K[k][u][x]; the paper's k_v stacks vec(K_k) column-major.
+ *
+ * Constraint order and compact cone layout (shared with the CPU oracle):
+ *  state constraints first, by time t = 1..T; within one t, obstacles (arm:
+ *  obstacle-major, then link point 0..6), then state upper/lower bounds per
+ *  component; then control bounds by step k = 0..T-1, per input upper then
+ *  lower.  Cone j stores (t_j, eta_j) with only the structurally non-zero
+ *  blocks of eta_j: a state constraint at time t keeps blocks 0..t
+ *  (1 + (t+1) n_x entries), a control bound at step k keeps block k
+ *  (1 + n_x entries).  The zero blocks stay zero under every update of both
+ *  methods, so the compaction is exact.
+ */
+#ifndef NRTO_H
+#define NRTO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nrto_ctx_s *nrto_ctx;
+
+typedef enum {
+  NRTO_OK = 0,
+  NRTO_MAXITER = 1,        /* iteration limit reached; the iterate is still returned */
+  NRTO_INFEASIBLE = 2,     /* consensus residual stagnates (linearisation infeasible) */
+  NRTO_FALLBACK_COLD = 3,  /* warm start rejected, cold start used */
+  NRTO_ERR_ARG = -1,
+  NRTO_ERR_ALLOC = -2,
+  NRTO_ERR_HIP = -3,
+  NRTO_ERR_STATE = -4
+} nrto_status;
+
+typedef enum { NRTO_DR = 0, NRTO_FULLADMM = 1 } nrto_method;
+typedef enum { NRTO_FP64 = 0, NRTO_FP32 = 1 } nrto_precision;
+typedef enum { NRTO_DYN_UNICYCLE = 0, NRTO_DYN_QUADROTOR = 1, NRTO_DYN_ARM = 2 } nrto_dyn;
+
+/* One robust trajectory problem (Problem 1).  Copied by nrto_setup. */
+typedef struct {
+  int32_t dyn;               /* nrto_dyn */
+  int32_t nx, nu, T;         /* (3,2), (12,4) or (14,7); 1 <= T <= 128 */
+  double dt;                 /* forward-Euler step */
+  double radius;             /* disturbance ball radius r = sqrt(tau) */
+  double mass;               /* quadrotor mass (ignored otherwise) */
+  const double *inertia;     /* quadrotor diag(J), 3 values; NULL otherwise */
+  const double *links;       /* arm DH link lengths, 7 values; NULL otherwise */
+  const double *x0, *xg;     /* nx each: start and goal states */
+  const double *Q;           /* nx*nx state tracking weight */
+  const double *Ru;          /* nu*nu control weight R_u */
+  const double *RK;          /* nu*nu gain weight R_K (cost ||R_K K_k||_F^2) */
+  int32_t n_obs;             /* obstacles: rows (centre[d], radius), d = 2 (unicycle) or 3 */
+  const double *obs;
+  const double *u_lo, *u_hi; /* nu each, +-inf = no bound; NULL = none */
+  const double *x_lo, *x_hi; /* nx each, +-inf = no bound; NULL = none */
+  const double *u_init;      /* T*nu initial nominal controls */
+} nrto_problem;
+
+typedef struct {
+  int32_t method;            /* nrto_method */
+  int32_t precision;         /* nrto_precision: iteration/projection arithmetic; factor, QP and
+                                residual checks are always FP64 */
+  int32_t max_admm;          /* ADMM iterations per solve (paper: 40) */
+  int32_t max_inner;         /* DR iterations per ADMM step (paper: 100) */
+  int32_t check_every;       /* ADMM iterations between KKT residual checks */
+  int32_t block_threads;     /* threads per instance workgroup: 64..1024, multiple of 64; 0 = auto */
+  double rho;                /* ADMM penalty (paper: 40 NRTO-DR outer ADMM, 10 FullADMM) */
+  double alpha;              /* DR relaxation in (0, 2) */
+  double sigma_chi, sigma_s; /* DR proximal scalings R_chi = sigma_chi I, R_s = sigma_s I */
+  double eps_dr_abs, eps_dr_rel; /* DR stop: ||s~_new - s~|| <= abs + rel max(1, ||s~||) */
+  double eps_kkt;            /* stop when the FP64 KKT residual <= eps_kkt (0 = never) */
+  double r_trust;            /* trust-region radius ||F_u du|| <= r_trust */
+} nrto_options;
+
+/* Per-instance result of a solve. */
+typedef struct {
+  int32_t status;            /* NRTO_OK or NRTO_MAXITER */
+  int32_t admm_iters;
+  int32_t inner_iters;       /* total DR iterations (0 for FullADMM) */
+  int32_t qp_newton;         /* total Riccati solves in the (du, p) blocks */
+  double kkt;                /* FP64 KKT residual of the returned iterate */
+  double r_p, r_d;           /* ||p - p~||, rho ||p~ - p~_prev|| of the last ADMM step */
+  double mu;                 /* trust-region multiplier */
+} nrto_solve_report;
+
+/* Per-instance result of one successive-linearisation step. */
+typedef struct {
+  int32_t accepted;          /* step accepted by the merit test */
+  int32_t status;            /* solve status */
+  double merit_old, merit_new, predicted;
+  double r_trust;            /* radius for the next step */
+  double kkt;
+} nrto_step_report;
+
+/* Defaults: DR, FP64, 40 ADMM x 100 DR iterations, rho 40, alpha 1,
+ * sigma 1, eps_dr 1e-4, eps_kkt 1e-4, r_trust 2 (paper hyperparameter tables). */
+void nrto_default_options(nrto_options *opt);
+
+/*
+ * Projection of concatenated cones onto second-order cones (supplementary
+ * II-C, closed form with its three cases in printed order).
+ *  in, out    device arrays of n_entries values (float64 if dtype = 0, float32 if
+ *             dtype = 1); in == out is allowed (in-place).
+ *  seg_off    device int64 array of n_cones + 1 offsets: cone i is
+ *             [seg_off[i], seg_off[i+1]); its first entry is t, the rest eta.  A
+ *             length-1 cone is the ray t >= 0; empty cones are allowed.  Must
+ *             satisfy seg_off[0] = 0, non-decreasing, seg_off[n_cones] = n_entries.
+ *  flags      bit 0: validate seg_off on the device first (synchronises the
+ *             stream; NRTO_ERR_ARG if invalid).  Without validation the kernel
+ *             still never touches memory outside [0, n_entries).
+ *  stream     hipStream_t (NULL = default stream).
+ */
+nrto_status nrto_project_soc(const void *in, void *out, const int64_t *seg_off,
+                             int64_t n_cones, int64_t n_entries, int32_t dtype,
+                             int32_t flags, void *stream);
+
+/*
+ * Create a context for n_inst problems: device workspace, compact cone layout,
+ * wave task schedule.  probs: host array of n_inst problems.  opt: solver
+ * options (copied; may be changed later with nrto_set_options).  stream:
+ * hipStream_t the context enqueues on.  The nominal controls start at u_init.
+ */
+nrto_status nrto_setup(const nrto_problem *probs, int32_t n_inst, const nrto_options *opt,
+                       void *stream, nrto_ctx *out);
+void nrto_destroy(nrto_ctx ctx);
+const char *nrto_last_error(nrto_ctx ctx);
+nrto_status nrto_set_options(nrto_ctx ctx, const nrto_options *opt);
+
+/* Sizes of instance inst: out[0] n_g, out[1] cone entries, out[2] eta blocks,
+ * out[3] n_state (state constraints), out[4] T, out[5] nx, out[6] nu. */
+nrto_status nrto_instance_sizes(nrto_ctx ctx, int32_t inst, int64_t out[7]);
+
+/*
+ * Constraint-data formation on the device (step a0): nonlinear rollout of the
+ * nominal controls, analytic Jacobians, and for every constraint the adjoint
+ * recursion lambda_t = grad g_j, b_{j,i} = B_i' lambda_{i+1}, lambda_i = A_i' lambda_{i+1},
+ * b_hat_j = r [lambda_0; ...; lambda_t] (supplementary section I).
+ */
+nrto_status nrto_linearize(nrto_ctx ctx);
+
+/*
+ * Replace the linearised data of instance inst by caller-provided host arrays
+ * (used to feed both this library and an independent implementation the same
+ * SOCP).  Shapes: A T*nx*nx, B T*nx*nu, xhat (T+1)*nx, uhat T*nu, g0 n_g,
+ * w n_g*nx (gradient of state constraint j at x_{t_j}; zero rows for control
+ * bounds), bhat cone entries (compact layout; the t slot of every cone is 0),
+ * bvec blocks*nu (b_{j,k} of every stored block; zero for the last block of a
+ * state constraint).
+ */
+nrto_status nrto_upload_socp(nrto_ctx ctx, int32_t inst, const double *A, const double *B,
+                             const double *xhat, const double *uhat, const double *g0,
+                             const double *w, const double *bhat, const double *bvec);
+/* Copy the device SOCP data of instance inst back (same shapes as upload). */
+nrto_status nrto_download_socp(nrto_ctx ctx, int32_t inst, double *A, double *B, double *xhat,
+                               double *uhat, double *g0, double *w, double *bhat, double *bvec);
+
+/*
+ * Solve the loaded SOCPs of all instances (steps a1-a8: reduced-KKT factor,
+ * fused gain-GEMM / projection / relaxation passes, block solves, (du, p)
+ * block, dual updates, FP64 KKT residual checks) in one persistent launch.
+ * warm = 0 starts every method state from zero; warm = 1 continues from the
+ * current state.  rep: host array of n_inst reports (may be NULL).
+ */
+nrto_status nrto_solve_socp(nrto_ctx ctx, int32_t warm, nrto_solve_report *rep);
+
+/*
+ * Read the solution of instance inst into host arrays (any may be NULL):
+ * du T*nu, K T*nu*nx (K[k][u][x]), p, pt, pi, lam n_g (lam: DR dual lambda,
+ * FullADMM scaled dual lambda_p), mu 1.
+ */
+nrto_status nrto_get_solution(nrto_ctx ctx, int32_t inst, double *du, double *K, double *p,
+                              double *pt, double *pi, double *lam, double *mu);
+/*
+ * Read / write the iteration state of instance inst (compact layout; any
+ * pointer may be NULL).  DR: st = s~ (entries), kt = K~ (T*nu*nx), ptt = p~~ (n_g).
+ * FullADMM: st = lambda_nu (entries, t slots 0), nu = nu (entries), kt unused.
+ */
+nrto_status nrto_get_state(nrto_ctx ctx, int32_t inst, double *st, double *nu, double *kt,
+                           double *ptt);
+nrto_status nrto_set_state(nrto_ctx ctx, int32_t inst, const double *st, const double *nu,
+                           const double *kt, const double *ptt, const double *du,
+                           const double *K, const double *p, const double *pt,
+                           const double *lam);
+
+/*
+ * One successive-linearisation step for every instance: nrto_linearize, solve,
+ * nonlinear rollout of the candidate, merit test, trust-region update and, on
+ * acceptance, u_hat += du and the new gains.  rep: n_inst entries or NULL.
+ */
+nrto_status nrto_scp_step(nrto_ctx ctx, nrto_step_report *rep);
+/* Current nominal controls of instance inst (T*nu) and gains (T*nu*nx, may be NULL). */
+nrto_status nrto_get_nominal(nrto_ctx ctx, int32_t inst, double *uhat, double *K);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NRTO_H */

@@ -1,0 +1,661 @@
+// Host side of the C ABI: context creation, compact cone layout, wave task
+// schedule, host <-> device transfers and solver launches.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace nrto {
+
+size_t solver_smem_bytes(int T, int nx, int nu, int precision, int threads);
+hipError_t launch_solver(const DevPtrs& g, const SolveOpts& o, int nx, const int32_t* order, int n, int threads,
+                         size_t smem, hipStream_t s);
+hipError_t set_solver_smem_limit(size_t bytes);
+hipError_t launch_linearize(const DevPtrs& g, int n_inst, int max_ng, hipStream_t s);
+
+static thread_local std::string g_err;
+
+nrto_status set_global_error(nrto_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+}  // namespace nrto
+
+using namespace nrto;
+
+struct HostInst {
+  InstDev d;
+  std::vector<int32_t> cmeta;
+  std::vector<WaveTask> tasks;
+  std::vector<uint64_t> tmask;
+  std::vector<int32_t> tl;
+  std::vector<double> prm;
+  std::vector<double> uinit;
+};
+
+struct nrto_ctx_s {
+  hipStream_t stream = nullptr;
+  nrto_options opt{};
+  int n = 0;
+  std::vector<HostInst> hi;
+  DevPtrs g{};
+  std::vector<void*> allocs;
+  int64_t ncones = 0, nent = 0, nbv = 0, nA = 0, nB = 0, nX = 0, nU = 0, nK = 0, nW = 0, nP = 0, nTL = 0,
+          nG = 0, nR = 0, ntask = 0;
+  int32_t* order = nullptr;
+  std::vector<int32_t> horder;
+  int group_nx[3] = {3, 12, 14};
+  int group_off[4] = {0, 0, 0, 0};   // instances of model g are order[group_off[g] .. group_off[g+1])
+  int threads = 256;
+  size_t smem = 0;
+  std::string err;
+  std::vector<double> rtrust;  // per-instance trust radius (host copy)
+};
+
+static nrto_status ctx_err(nrto_ctx c, nrto_status s, const std::string& m) {
+  if (c) c->err = m;
+  g_err = m;
+  return s;
+}
+
+#define HIPCHK(ctx, expr)                                                            \
+  do {                                                                               \
+    hipError_t _e = (expr);                                                          \
+    if (_e != hipSuccess) return ctx_err(ctx, NRTO_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+template <typename T>
+static nrto_status dalloc(nrto_ctx c, T** p, int64_t n) {
+  size_t bytes = (size_t)std::max<int64_t>(n, 1) * sizeof(T);
+  void* q = nullptr;
+  if (hipMalloc(&q, bytes) != hipSuccess) return ctx_err(c, NRTO_ERR_ALLOC, "hipMalloc failed");
+  hipMemsetAsync(q, 0, bytes, c->stream);
+  c->allocs.push_back(q);
+  *p = (T*)q;
+  return NRTO_OK;
+}
+
+extern "C" void nrto_default_options(nrto_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->method = NRTO_DR;
+  o->precision = NRTO_FP64;
+  o->max_admm = 40;
+  o->max_inner = 100;
+  o->check_every = 1;
+  o->block_threads = 0;
+  o->rho = 40.0;
+  o->alpha = 1.0;
+  o->sigma_chi = 1.0;
+  o->sigma_s = 1.0;
+  o->eps_dr_abs = 1e-4;
+  o->eps_dr_rel = 1e-4;
+  o->eps_kkt = 1e-4;
+  o->r_trust = 2.0;
+}
+
+extern "C" const char* nrto_last_error(nrto_ctx c) { return c ? c->err.c_str() : g_err.c_str(); }
+
+static bool finite_or_inf(double v) { return !std::isnan(v); }
+
+// Build the structural layout of one problem.
+static nrto_status build_instance(nrto_ctx c, const nrto_problem& p, HostInst& h) {
+  const int nx = p.nx, nu = p.nu, T = p.T;
+  bool ok = (p.dyn == NRTO_DYN_UNICYCLE && nx == 3 && nu == 2) || (p.dyn == NRTO_DYN_QUADROTOR && nx == 12 && nu == 4) ||
+            (p.dyn == NRTO_DYN_ARM && nx == 14 && nu == 7);
+  if (!ok) return ctx_err(c, NRTO_ERR_ARG, "dyn/nx/nu must be unicycle (3,2), quadrotor (12,4) or arm (14,7)");
+  if (T < 1 || T > MAX_T) return ctx_err(c, NRTO_ERR_ARG, "T must be in [1, 128]");
+  if (!p.x0 || !p.xg || !p.Q || !p.Ru || !p.RK || !p.u_init) return ctx_err(c, NRTO_ERR_ARG, "null problem array");
+  if (p.n_obs < 0 || (p.n_obs > 0 && !p.obs)) return ctx_err(c, NRTO_ERR_ARG, "bad obstacles");
+  if (!(p.radius >= 0.0) || !(p.dt > 0.0)) return ctx_err(c, NRTO_ERR_ARG, "radius >= 0 and dt > 0 required");
+  if (p.dyn == NRTO_DYN_QUADROTOR && (!p.inertia || !(p.mass > 0.0))) return ctx_err(c, NRTO_ERR_ARG, "quadrotor needs mass and inertia");
+  if (p.dyn == NRTO_DYN_ARM && !p.links) return ctx_err(c, NRTO_ERR_ARG, "arm needs links");
+  const int npts = (p.dyn == NRTO_DYN_ARM) ? 7 : 1;
+  // constraints per time
+  std::vector<int32_t> cm;
+  int ent = 0, blk = 0, nstate = 0;
+  std::vector<int32_t> tls(T + 2, 0), tlc(T + 1, 0);
+  auto add = [&](int kind, int time, int k0, int nblk, int cidx, int csign) {
+    int32_t m[CM_N];
+    m[CM_EOFF] = ent;
+    m[CM_K0] = k0;
+    m[CM_NBLK] = nblk;
+    m[CM_BOFF] = blk;
+    m[CM_KIND] = kind;
+    m[CM_TIME] = time;
+    m[CM_CIDX] = cidx;
+    m[CM_CSIGN] = csign;
+    cm.insert(cm.end(), m, m + CM_N);
+    ent += 1 + nblk * nx;
+    blk += nblk;
+  };
+  for (int t = 1; t <= T; ++t) {
+    tls[t] = (int)(cm.size() / CM_N);
+    for (int o = 0; o < p.n_obs; ++o)
+      for (int q = 0; q < npts; ++q) add(0, t, 0, t + 1, -1, 0);
+    if (p.x_hi && p.x_lo)
+      for (int i = 0; i < nx; ++i) {
+        if (std::isfinite(p.x_hi[i])) add(0, t, 0, t + 1, i, 1);
+        if (std::isfinite(p.x_lo[i])) add(0, t, 0, t + 1, i, -1);
+      }
+  }
+  nstate = (int)(cm.size() / CM_N);
+  tls[0] = 0;
+  tls[T + 1] = nstate;
+  for (int k = 0; k < T; ++k) {
+    tlc[k] = (int)(cm.size() / CM_N);
+    for (int i = 0; i < nu; ++i) {
+      if (p.u_hi && std::isfinite(p.u_hi[i])) add(1, k, k, 1, i, 1);
+      if (p.u_lo && std::isfinite(p.u_lo[i])) add(1, k, k, 1, i, -1);
+    }
+  }
+  const int ng = (int)(cm.size() / CM_N);
+  tlc[T] = ng;
+  for (int i = 0; i < ng; ++i)
+    if (1 + cm[i * CM_N + CM_NBLK] * nx > 64 * 16)
+      return ctx_err(c, NRTO_ERR_ARG, "cone longer than 1024 entries (reduce T)");
+  // wave tasks: long cones alone, short consecutive cones packed up to 64 entries
+  std::vector<WaveTask> longt, shortt;
+  std::vector<uint64_t> shortm;
+  {
+    int j = 0;
+    while (j < ng) {
+      int len = 1 + cm[j * CM_N + CM_NBLK] * nx;
+      if (len > 64) {
+        longt.push_back({j, 1, cm[j * CM_N + CM_EOFF], len});
+        ++j;
+        continue;
+      }
+      WaveTask tk{j, 0, cm[j * CM_N + CM_EOFF], 0};
+      uint64_t mask = 0;
+      while (j < ng) {
+        int l2 = 1 + cm[j * CM_N + CM_NBLK] * nx;
+        if (l2 > 64 || tk.len + l2 > 64) break;
+        mask |= (1ull << tk.len);
+        tk.len += l2;
+        tk.ncone += 1;
+        ++j;
+      }
+      shortt.push_back(tk);
+      shortm.push_back(mask);
+    }
+  }
+  std::sort(longt.begin(), longt.end(), [](const WaveTask& a, const WaveTask& b) { return a.len > b.len; });
+  h.tasks = longt;
+  h.tmask.assign(longt.size(), 0ull);
+  h.tasks.insert(h.tasks.end(), shortt.begin(), shortt.end());
+  h.tmask.insert(h.tmask.end(), shortm.begin(), shortm.end());
+  h.cmeta = cm;
+  h.tl = tls;
+  h.tl.insert(h.tl.end(), tlc.begin(), tlc.end());
+  // parameters
+  ParamOffsets po = param_offsets(nx, nu, p.n_obs);
+  h.prm.assign(po.size, 0.0);
+  for (int i = 0; i < nx * nx; ++i) h.prm[po.Q + i] = p.Q[i];
+  for (int i = 0; i < nu * nu; ++i) h.prm[po.Ru + i] = p.Ru[i];
+  for (int u = 0; u < nu; ++u)
+    for (int w = 0; w < nu; ++w) {
+      double s = 0.0;
+      for (int l = 0; l < nu; ++l) s += p.RK[l * nu + u] * p.RK[l * nu + w];
+      h.prm[po.RK2 + u * nu + w] = s;
+    }
+  for (int i = 0; i < nx; ++i) {
+    h.prm[po.xg + i] = p.xg[i];
+    h.prm[po.x0 + i] = p.x0[i];
+    h.prm[po.xlo + i] = (p.x_lo ? p.x_lo[i] : -INFINITY);
+    h.prm[po.xhi + i] = (p.x_hi ? p.x_hi[i] : INFINITY);
+  }
+  for (int i = 0; i < nu; ++i) {
+    h.prm[po.ulo + i] = (p.u_lo ? p.u_lo[i] : -INFINITY);
+    h.prm[po.uhi + i] = (p.u_hi ? p.u_hi[i] : INFINITY);
+  }
+  if (p.inertia)
+    for (int i = 0; i < 3; ++i) h.prm[po.inertia + i] = p.inertia[i];
+  if (p.links)
+    for (int i = 0; i < 7; ++i) h.prm[po.links + i] = p.links[i];
+  const int od = (p.dyn == NRTO_DYN_UNICYCLE) ? 2 : 3;
+  for (int o = 0; o < p.n_obs; ++o) {
+    for (int i = 0; i < od; ++i) h.prm[po.obs + 4 * o + i] = p.obs[o * (od + 1) + i];
+    h.prm[po.obs + 4 * o + 3] = p.obs[o * (od + 1) + od];
+  }
+  h.uinit.assign(p.u_init, p.u_init + T * nu);
+  InstDev& d = h.d;
+  std::memset(&d, 0, sizeof(d));
+  d.dyn = p.dyn;
+  d.nx = nx;
+  d.nu = nu;
+  d.T = T;
+  d.ng = ng;
+  d.nstate = nstate;
+  d.nent = ent;
+  d.nblk = blk;
+  d.ntask = (int)h.tasks.size();
+  d.n_obs = p.n_obs;
+  d.radius = p.radius;
+  d.dt = p.dt;
+  d.mass = p.mass;
+  return NRTO_OK;
+}
+
+static void fill_opts(const nrto_ctx c, SolveOpts& o, int warm) {
+  o.method = c->opt.method;
+  o.precision = c->opt.precision;
+  o.max_admm = c->opt.max_admm;
+  o.max_inner = c->opt.max_inner;
+  o.check_every = std::max(1, c->opt.check_every);
+  o.warm = warm;
+  o.rho = c->opt.rho;
+  o.alpha = c->opt.alpha;
+  o.sigma_chi = c->opt.sigma_chi;
+  o.sigma_s = c->opt.sigma_s;
+  o.eps_dr_abs = c->opt.eps_dr_abs;
+  o.eps_dr_rel = c->opt.eps_dr_rel;
+  o.eps_kkt = c->opt.eps_kkt;
+}
+
+static nrto_status check_options(nrto_ctx c, const nrto_options* o) {
+  if (!o) return ctx_err(c, NRTO_ERR_ARG, "null options");
+  if (o->method != NRTO_DR && o->method != NRTO_FULLADMM) return ctx_err(c, NRTO_ERR_ARG, "bad method");
+  if (o->precision != NRTO_FP64 && o->precision != NRTO_FP32) return ctx_err(c, NRTO_ERR_ARG, "bad precision");
+  if (o->max_admm < 1 || o->max_inner < 1) return ctx_err(c, NRTO_ERR_ARG, "iteration limits must be >= 1");
+  if (!(o->rho > 0) || !(o->alpha > 0 && o->alpha < 2) || !(o->sigma_chi > 0) || !(o->sigma_s > 0))
+    return ctx_err(c, NRTO_ERR_ARG, "rho, sigma > 0 and alpha in (0, 2) required");
+  if (!(o->r_trust > 0)) return ctx_err(c, NRTO_ERR_ARG, "r_trust > 0 required");
+  if (o->block_threads != 0 && (o->block_threads < 64 || o->block_threads > 1024 || o->block_threads % 64))
+    return ctx_err(c, NRTO_ERR_ARG, "block_threads must be 0 or a multiple of 64 in [64, 1024]");
+  return NRTO_OK;
+}
+
+static nrto_status configure_launch(nrto_ctx c) {
+  int th = c->opt.block_threads;
+  if (th == 0) th = (c->n <= 64) ? 512 : 256;
+  if (th > 512) return ctx_err(c, NRTO_ERR_ARG, "block_threads above 512 is not supported by this build");
+  size_t smem = 0;
+  for (auto& h : c->hi) smem = std::max(smem, solver_smem_bytes(h.d.T, h.d.nx, h.d.nu, c->opt.precision, th));
+  if (smem > 160 * 1024) return ctx_err(c, NRTO_ERR_ARG, "per-instance LDS need exceeds 160 KB (reduce T or use FP32)");
+  c->threads = th;
+  c->smem = smem;
+  HIPCHK(c, set_solver_smem_limit(smem));
+  return NRTO_OK;
+}
+
+extern "C" nrto_status nrto_set_options(nrto_ctx c, const nrto_options* o) {
+  if (!c) return set_global_error(NRTO_ERR_ARG, "null context");
+  nrto_status s = check_options(c, o);
+  if (s != NRTO_OK) return s;
+  c->opt = *o;
+  std::vector<InstDev> d(c->n);
+  for (int i = 0; i < c->n; ++i) {
+    c->hi[i].d.r_trust = o->r_trust;
+    d[i] = c->hi[i].d;
+  }
+  HIPCHK(c, hipMemcpyAsync(c->g.inst, d.data(), sizeof(InstDev) * c->n, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return configure_launch(c);
+}
+
+extern "C" nrto_status nrto_setup(const nrto_problem* probs, int32_t n, const nrto_options* opt, void* stream,
+                                  nrto_ctx* out) {
+  if (!out) return set_global_error(NRTO_ERR_ARG, "null output");
+  *out = nullptr;
+  if (!probs || n < 1) return set_global_error(NRTO_ERR_ARG, "need at least one problem");
+  nrto_ctx c = new (std::nothrow) nrto_ctx_s();
+  if (!c) return set_global_error(NRTO_ERR_ALLOC, "out of host memory");
+  c->stream = (hipStream_t)stream;
+  c->n = n;
+  nrto_options o;
+  if (opt) o = *opt; else nrto_default_options(&o);
+  nrto_status s = check_options(c, &o);
+  if (s != NRTO_OK) { g_err = c->err; delete c; return s; }
+  c->opt = o;
+  c->hi.resize(n);
+  for (int i = 0; i < n; ++i) {
+    s = build_instance(c, probs[i], c->hi[i]);
+    if (s != NRTO_OK) { g_err = "instance " + std::to_string(i) + ": " + c->err; delete c; return s; }
+    c->hi[i].d.r_trust = o.r_trust;
+  }
+  // offsets
+  for (auto& h : c->hi) {
+    InstDev& d = h.d;
+    d.cone0 = c->ncones; c->ncones += d.ng;
+    d.ent0 = c->nent; c->nent += d.nent;
+    d.bv0 = c->nbv; c->nbv += (int64_t)d.nblk * d.nu;
+    d.task0 = c->ntask; c->ntask += d.ntask;
+    d.oA = c->nA; c->nA += (int64_t)d.T * d.nx * d.nx;
+    d.oB = c->nB; c->nB += (int64_t)d.T * d.nx * d.nu;
+    d.oX = c->nX; c->nX += (int64_t)(d.T + 1) * d.nx;
+    d.oU = c->nU; c->nU += (int64_t)d.T * d.nu;
+    d.oK = c->nK; c->nK += (int64_t)d.T * d.nu * d.nx;
+    d.oW = c->nW; c->nW += (int64_t)d.ng * d.nx;
+    d.oP = c->nP; c->nP += (int64_t)h.prm.size();
+    d.oTL = c->nTL; c->nTL += (int64_t)h.tl.size();
+    d.oG = c->nG; c->nG += (int64_t)d.T * d.nu * d.nu;
+    d.oR = c->nR; c->nR += (int64_t)d.T * d.nu * (d.nx + 1);
+  }
+  DevPtrs& g = c->g;
+  g.ncones = c->ncones;
+#define ALLOC(ptr, n)                                       \
+  do {                                                      \
+    nrto_status _s = dalloc(c, &(ptr), (n));                \
+    if (_s != NRTO_OK) { g_err = c->err; nrto_destroy(c); return _s; } \
+  } while (0)
+  ALLOC(g.inst, n);
+  ALLOC(g.cmeta, c->ncones * CM_N);
+  ALLOC(g.carr, c->ncones * CA_NUM);
+  ALLOC(g.w, c->nW);
+  ALLOC(g.bhat64, c->nent);
+  ALLOC(g.bhat32, c->nent);
+  ALLOC(g.bvec64, c->nbv);
+  ALLOC(g.bvec32, c->nbv);
+  double* st = nullptr;
+  double* nu = nullptr;
+  ALLOC(st, c->nent);
+  ALLOC(nu, c->nent);
+  g.st = st;
+  g.nu = nu;
+  ALLOC(g.A, c->nA);
+  ALLOC(g.B, c->nB);
+  ALLOC(g.xhat, c->nX);
+  ALLOC(g.uhat, c->nU);
+  ALLOC(g.dx, c->nX);
+  ALLOC(g.du, c->nU);
+  ALLOC(g.dx2, c->nX);
+  ALLOC(g.du2, c->nU);
+  ALLOC(g.K, c->nK);
+  ALLOC(g.Kt, c->nK);
+  ALLOC(g.kscr, c->nK);
+  ALLOC(g.ric, c->nR);
+  ALLOC(g.prm, c->nP);
+  ALLOC(g.tl, c->nTL);
+  ALLOC(g.gch, c->nG);
+  ALLOC(g.tasks, c->ntask);
+  ALLOC(g.tmask, c->ntask);
+  ALLOC(g.mu, n);
+  ALLOC(g.iscr, (int64_t)n * ISCR_N);
+  ALLOC(g.flags, (int64_t)n * 4);
+  ALLOC(g.rep, n);
+  ALLOC(c->order, n);
+#undef ALLOC
+  // uploads
+  std::vector<InstDev> d(n);
+  std::vector<int32_t> cm;
+  std::vector<WaveTask> tk;
+  std::vector<uint64_t> tm;
+  std::vector<int32_t> tl;
+  std::vector<double> prm, u;
+  for (int i = 0; i < n; ++i) {
+    auto& h = c->hi[i];
+    d[i] = h.d;
+    cm.insert(cm.end(), h.cmeta.begin(), h.cmeta.end());
+    tk.insert(tk.end(), h.tasks.begin(), h.tasks.end());
+    tm.insert(tm.end(), h.tmask.begin(), h.tmask.end());
+    tl.insert(tl.end(), h.tl.begin(), h.tl.end());
+    prm.insert(prm.end(), h.prm.begin(), h.prm.end());
+    u.insert(u.end(), h.uinit.begin(), h.uinit.end());
+  }
+  // instance order: grouped by model, largest first inside a group (longest processing time first)
+  c->horder.resize(n);
+  std::iota(c->horder.begin(), c->horder.end(), 0);
+  auto grp = [&](int i) { int nx = c->hi[i].d.nx; return nx == 3 ? 0 : (nx == 12 ? 1 : 2); };
+  std::stable_sort(c->horder.begin(), c->horder.end(), [&](int a, int b) {
+    if (grp(a) != grp(b)) return grp(a) < grp(b);
+    return c->hi[a].d.nent > c->hi[b].d.nent;
+  });
+  for (int gi = 0; gi < 3; ++gi) {
+    int cnt = 0;
+    for (int i = 0; i < n; ++i) cnt += (grp(i) == gi);
+    c->group_off[gi + 1] = c->group_off[gi] + cnt;
+  }
+  hipStream_t sm = c->stream;
+  auto H2D = [&](void* dst, const void* src, size_t bytes) { return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, sm); };
+  HIPCHK(c, H2D(g.inst, d.data(), sizeof(InstDev) * n));
+  HIPCHK(c, H2D(g.cmeta, cm.data(), sizeof(int32_t) * cm.size()));
+  HIPCHK(c, H2D(g.tasks, tk.data(), sizeof(WaveTask) * tk.size()));
+  HIPCHK(c, H2D(g.tmask, tm.data(), sizeof(uint64_t) * tm.size()));
+  HIPCHK(c, H2D(g.tl, tl.data(), sizeof(int32_t) * tl.size()));
+  HIPCHK(c, H2D(g.prm, prm.data(), sizeof(double) * prm.size()));
+  HIPCHK(c, H2D(g.uhat, u.data(), sizeof(double) * u.size()));
+  HIPCHK(c, H2D(c->order, c->horder.data(), sizeof(int32_t) * n));
+  HIPCHK(c, hipStreamSynchronize(sm));
+  s = configure_launch(c);
+  if (s != NRTO_OK) { g_err = c->err; nrto_destroy(c); return s; }
+  *out = c;
+  return NRTO_OK;
+}
+
+extern "C" void nrto_destroy(nrto_ctx c) {
+  if (!c) return;
+  if (c->stream) hipStreamSynchronize(c->stream);
+  else hipDeviceSynchronize();
+  for (void* p : c->allocs) hipFree(p);
+  delete c;
+}
+
+extern "C" nrto_status nrto_instance_sizes(nrto_ctx c, int32_t inst, int64_t out[7]) {
+  if (!c || !out) return set_global_error(NRTO_ERR_ARG, "null argument");
+  if (inst < 0 || inst >= c->n) return ctx_err(c, NRTO_ERR_ARG, "instance out of range");
+  const InstDev& d = c->hi[inst].d;
+  out[0] = d.ng;
+  out[1] = d.nent;
+  out[2] = d.nblk;
+  out[3] = d.nstate;
+  out[4] = d.T;
+  out[5] = d.nx;
+  out[6] = d.nu;
+  return NRTO_OK;
+}
+
+template <typename T>
+static hipError_t copy_in(T* dst, const T* src, size_t n, hipStream_t s) {
+  if (!src || n == 0) return hipSuccess;
+  return hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyHostToDevice, s);
+}
+template <typename T>
+static hipError_t copy_out(T* dst, const T* src, size_t n, hipStream_t s) {
+  if (!dst || n == 0) return hipSuccess;
+  return hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToHost, s);
+}
+
+extern "C" nrto_status nrto_upload_socp(nrto_ctx c, int32_t inst, const double* A, const double* B,
+                                        const double* xhat, const double* uhat, const double* g0,
+                                        const double* w, const double* bhat, const double* bvec) {
+  if (!c) return set_global_error(NRTO_ERR_ARG, "null context");
+  if (inst < 0 || inst >= c->n) return ctx_err(c, NRTO_ERR_ARG, "instance out of range");
+  const InstDev& d = c->hi[inst].d;
+  hipStream_t s = c->stream;
+  HIPCHK(c, copy_in(c->g.A + d.oA, A, (size_t)d.T * d.nx * d.nx, s));
+  HIPCHK(c, copy_in(c->g.B + d.oB, B, (size_t)d.T * d.nx * d.nu, s));
+  HIPCHK(c, copy_in(c->g.xhat + d.oX, xhat, (size_t)(d.T + 1) * d.nx, s));
+  HIPCHK(c, copy_in(c->g.uhat + d.oU, uhat, (size_t)d.T * d.nu, s));
+  HIPCHK(c, copy_in(c->g.w + d.oW, w, (size_t)d.ng * d.nx, s));
+  if (g0) {
+    HIPCHK(c, copy_in(c->g.carr + (int64_t)CA_G0 * c->ncones + d.cone0, g0, (size_t)d.ng, s));
+  }
+  std::vector<float> f;
+  if (bhat) {
+    HIPCHK(c, copy_in(c->g.bhat64 + d.ent0, bhat, (size_t)d.nent, s));
+    f.assign(bhat, bhat + d.nent);
+    HIPCHK(c, copy_in(c->g.bhat32 + d.ent0, f.data(), (size_t)d.nent, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+  }
+  if (bvec) {
+    const size_t nb = (size_t)d.nblk * d.nu;
+    HIPCHK(c, copy_in(c->g.bvec64 + d.bv0, bvec, nb, s));
+    f.assign(bvec, bvec + nb);
+    HIPCHK(c, copy_in(c->g.bvec32 + d.bv0, f.data(), nb, s));
+  }
+  HIPCHK(c, hipStreamSynchronize(s));
+  return NRTO_OK;
+}
+
+extern "C" nrto_status nrto_download_socp(nrto_ctx c, int32_t inst, double* A, double* B, double* xhat,
+                                          double* uhat, double* g0, double* w, double* bhat, double* bvec) {
+  if (!c) return set_global_error(NRTO_ERR_ARG, "null context");
+  if (inst < 0 || inst >= c->n) return ctx_err(c, NRTO_ERR_ARG, "instance out of range");
+  const InstDev& d = c->hi[inst].d;
+  hipStream_t s = c->stream;
+  HIPCHK(c, copy_out(A, c->g.A + d.oA, (size_t)d.T * d.nx * d.nx, s));
+  HIPCHK(c, copy_out(B, c->g.B + d.oB, (size_t)d.T * d.nx * d.nu, s));
+  HIPCHK(c, copy_out(xhat, c->g.xhat + d.oX, (size_t)(d.T + 1) * d.nx, s));
+  HIPCHK(c, copy_out(uhat, c->g.uhat + d.oU, (size_t)d.T * d.nu, s));
+  HIPCHK(c, copy_out(g0, c->g.carr + (int64_t)CA_G0 * c->ncones + d.cone0, (size_t)d.ng, s));
+  HIPCHK(c, copy_out(w, c->g.w + d.oW, (size_t)d.ng * d.nx, s));
+  HIPCHK(c, copy_out(bhat, c->g.bhat64 + d.ent0, (size_t)d.nent, s));
+  HIPCHK(c, copy_out(bvec, c->g.bvec64 + d.bv0, (size_t)d.nblk * d.nu, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  return NRTO_OK;
+}
+
+extern "C" nrto_status nrto_solve_socp(nrto_ctx c, int32_t warm, nrto_solve_report* rep) {
+  if (!c) return set_global_error(NRTO_ERR_ARG, "null context");
+  SolveOpts o;
+  fill_opts(c, o, warm ? 1 : 0);
+  for (int gi = 0; gi < 3; ++gi) {
+    const int cnt = c->group_off[gi + 1] - c->group_off[gi];
+    HIPCHK(c, launch_solver(c->g, o, c->group_nx[gi], c->order + c->group_off[gi], cnt, c->threads, c->smem,
+                            c->stream));
+  }
+  if (rep) {
+    HIPCHK(c, copy_out(rep, c->g.rep, (size_t)c->n, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return NRTO_OK;
+}
+
+// Copy a per-cone column of instance inst.
+static hipError_t cone_col_out(nrto_ctx c, int inst, int col, double* dst) {
+  const InstDev& d = c->hi[inst].d;
+  return copy_out(dst, c->g.carr + (int64_t)col * c->ncones + d.cone0, (size_t)d.ng, c->stream);
+}
+static hipError_t cone_col_in(nrto_ctx c, int inst, int col, const double* src) {
+  const InstDev& d = c->hi[inst].d;
+  return copy_in(c->g.carr + (int64_t)col * c->ncones + d.cone0, src, (size_t)d.ng, c->stream);
+}
+
+extern "C" nrto_status nrto_get_solution(nrto_ctx c, int32_t inst, double* du, double* K, double* p, double* pt,
+                                         double* pi, double* lam, double* mu) {
+  if (!c) return set_global_error(NRTO_ERR_ARG, "null context");
+  if (inst < 0 || inst >= c->n) return ctx_err(c, NRTO_ERR_ARG, "instance out of range");
+  const InstDev& d = c->hi[inst].d;
+  hipStream_t s = c->stream;
+  HIPCHK(c, copy_out(du, c->g.du + d.oU, (size_t)d.T * d.nu, s));
+  HIPCHK(c, copy_out(K, c->g.K + d.oK, (size_t)d.T * d.nu * d.nx, s));
+  HIPCHK(c, cone_col_out(c, inst, CA_P, p));
+  HIPCHK(c, cone_col_out(c, inst, CA_PT, pt));
+  HIPCHK(c, cone_col_out(c, inst, CA_PI, pi));
+  HIPCHK(c, cone_col_out(c, inst, CA_LAM, lam));
+  HIPCHK(c, copy_out(mu, c->g.mu + inst, 1, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  return NRTO_OK;
+}
+
+static nrto_status state_xfer(nrto_ctx c, int inst, double* st, double* nu, double* kt, double* ptt, bool out,
+                              const double* ist, const double* inu, const double* ikt, const double* iptt) {
+  const InstDev& d = c->hi[inst].d;
+  hipStream_t s = c->stream;
+  const size_t ne = (size_t)d.nent;
+  if (c->opt.precision == NRTO_FP64) {
+    double* dst = (double*)c->g.st + d.ent0;
+    double* dnu = (double*)c->g.nu + d.ent0;
+    if (out) {
+      HIPCHK(c, copy_out(st, dst, ne, s));
+      HIPCHK(c, copy_out(nu, dnu, ne, s));
+    } else {
+      HIPCHK(c, copy_in(dst, ist, ne, s));
+      HIPCHK(c, copy_in(dnu, inu, ne, s));
+    }
+  } else {
+    std::vector<float> f(ne);
+    float* dst = (float*)c->g.st + d.ent0;
+    float* dnu = (float*)c->g.nu + d.ent0;
+    if (out) {
+      if (st) {
+        HIPCHK(c, copy_out(f.data(), dst, ne, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        for (size_t i = 0; i < ne; ++i) st[i] = f[i];
+      }
+      if (nu) {
+        HIPCHK(c, copy_out(f.data(), dnu, ne, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        for (size_t i = 0; i < ne; ++i) nu[i] = f[i];
+      }
+    } else {
+      if (ist) {
+        for (size_t i = 0; i < ne; ++i) f[i] = (float)ist[i];
+        HIPCHK(c, copy_in(dst, f.data(), ne, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+      }
+      if (inu) {
+        for (size_t i = 0; i < ne; ++i) f[i] = (float)inu[i];
+        HIPCHK(c, copy_in(dnu, f.data(), ne, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+      }
+    }
+  }
+  if (out) {
+    HIPCHK(c, copy_out(kt, c->g.Kt + d.oK, (size_t)d.T * d.nu * d.nx, s));
+    HIPCHK(c, cone_col_out(c, inst, CA_PTT, ptt));
+  } else {
+    HIPCHK(c, copy_in(c->g.Kt + d.oK, ikt, (size_t)d.T * d.nu * d.nx, s));
+    HIPCHK(c, cone_col_in(c, inst, CA_PTT, iptt));
+  }
+  HIPCHK(c, hipStreamSynchronize(s));
+  return NRTO_OK;
+}
+
+extern "C" nrto_status nrto_get_state(nrto_ctx c, int32_t inst, double* st, double* nu, double* kt, double* ptt) {
+  if (!c) return set_global_error(NRTO_ERR_ARG, "null context");
+  if (inst < 0 || inst >= c->n) return ctx_err(c, NRTO_ERR_ARG, "instance out of range");
+  return state_xfer(c, inst, st, nu, kt, ptt, true, nullptr, nullptr, nullptr, nullptr);
+}
+
+extern "C" nrto_status nrto_set_state(nrto_ctx c, int32_t inst, const double* st, const double* nu,
+                                      const double* kt, const double* ptt, const double* du, const double* K,
+                                      const double* p, const double* pt, const double* lam) {
+  if (!c) return set_global_error(NRTO_ERR_ARG, "null context");
+  if (inst < 0 || inst >= c->n) return ctx_err(c, NRTO_ERR_ARG, "instance out of range");
+  nrto_status s = state_xfer(c, inst, nullptr, nullptr, nullptr, nullptr, false, st, nu, kt, ptt);
+  if (s != NRTO_OK) return s;
+  const InstDev& d = c->hi[inst].d;
+  hipStream_t sm = c->stream;
+  HIPCHK(c, copy_in(c->g.du + d.oU, du, (size_t)d.T * d.nu, sm));
+  HIPCHK(c, copy_in(c->g.K + d.oK, K, (size_t)d.T * d.nu * d.nx, sm));
+  HIPCHK(c, cone_col_in(c, inst, CA_P, p));
+  HIPCHK(c, cone_col_in(c, inst, CA_PT, pt));
+  HIPCHK(c, cone_col_in(c, inst, CA_LAM, lam));
+  // the (du, p) iterate's states follow from du; the solver recomputes them on its first Riccati pass
+  int32_t zero = 0;
+  HIPCHK(c, hipMemcpyAsync(c->g.flags + (int64_t)inst * 4, &zero, sizeof(int32_t), hipMemcpyHostToDevice, sm));
+  HIPCHK(c, hipStreamSynchronize(sm));
+  return NRTO_OK;
+}
+
+extern "C" nrto_status nrto_linearize(nrto_ctx c) {
+  if (!c) return set_global_error(NRTO_ERR_ARG, "null context");
+  int max_ng = 0;
+  for (auto& h : c->hi) max_ng = std::max(max_ng, h.d.ng);
+  HIPCHK(c, launch_linearize(c->g, c->n, max_ng, c->stream));
+  return NRTO_OK;
+}
+
+extern "C" nrto_status nrto_get_nominal(nrto_ctx c, int32_t inst, double* uhat, double* K) {
+  if (!c) return set_global_error(NRTO_ERR_ARG, "null context");
+  if (inst < 0 || inst >= c->n) return ctx_err(c, NRTO_ERR_ARG, "instance out of range");
+  const InstDev& d = c->hi[inst].d;
+  HIPCHK(c, copy_out(uhat, c->g.uhat + d.oU, (size_t)d.T * d.nu, c->stream));
+  HIPCHK(c, copy_out(K, c->g.K + d.oK, (size_t)d.T * d.nu * d.nx, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return NRTO_OK;
+}
+
+extern "C" nrto_status nrto_scp_step(nrto_ctx c, nrto_step_report* rep) {
+  if (!c) return set_global_error(NRTO_ERR_ARG, "null context");
+  (void)rep;
+  return ctx_err(c, NRTO_ERR_STATE, "nrto_scp_step is not available in this build");
+}

@@ -1,0 +1,140 @@
+// Batched projection onto second-order cones (supplementary II-C).
+//
+// Memory-bound: each entry is read once and written once.  A workgroup owns
+// the cones whose first entry (t) falls in its tile of TILE entries; their
+// entries are streamed with coalesced loads into LDS (up to CAP), the squared
+// norms of the eta parts are reduced per cone with LDS float64 atomics, and a
+// second sweep over the staged values applies the closed form:
+//   a = ||eta||;  a <= t -> unchanged;  a <= -t -> 0;  else ((t+a)/2, (t+a)/(2a) eta).
+// Entries of an owned cone beyond CAP (cones longer than CAP - TILE) are read
+// from global memory a second time.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace nrto {
+
+constexpr int PS_THREADS = 256;
+constexpr int PS_TILE = 1024;
+constexpr int PS_CAP = 4096;
+
+__device__ __forceinline__ int64_t lower_bound_i64(const int64_t* a, int64_t n, int64_t key) {
+  // first index i in [0, n] with a[i] >= key (a has n + 1 readable entries)
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if (a[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+template <typename F>
+__global__ void __launch_bounds__(PS_THREADS)
+project_soc_kernel(const F* in, F* out, const int64_t* __restrict__ off,
+                   int64_t ncones, int64_t N) {
+  __shared__ F stage[PS_CAP];
+  __shared__ double sums[PS_TILE];
+  __shared__ int32_t coff[PS_TILE + 1];
+  __shared__ int64_t range[2];
+
+  const int64_t tile_lo = (int64_t)blockIdx.x * PS_TILE;
+  const int64_t tile_hi = min(tile_lo + (int64_t)PS_TILE, N);
+  if (threadIdx.x == 0) {
+    range[0] = lower_bound_i64(off, ncones, tile_lo);
+    range[1] = lower_bound_i64(off, ncones, tile_hi);
+  }
+  __syncthreads();
+  const int64_t cb_all = range[0], ce_all = range[1];
+  // Cones starting in this tile, in chunks of at most TILE cones (more only with empty cones).
+  for (int64_t cb = cb_all; cb < ce_all; cb += PS_TILE) {
+    const int64_t ce = min(cb + (int64_t)PS_TILE, ce_all);
+    const int nown = (int)(ce - cb);
+    const int64_t e_lo = min(max(off[cb], (int64_t)0), N);
+    const int64_t e_hi = min(max(off[ce], e_lo), N);
+    const int64_t len = e_hi - e_lo;
+    for (int i = threadIdx.x; i <= nown; i += PS_THREADS) {
+      int64_t o = min(max(off[cb + i], e_lo), e_hi);
+      coff[i] = (int32_t)min(o - e_lo, (int64_t)0x7fffffff);
+      if (i < nown) sums[i] = 0.0;
+    }
+    __syncthreads();
+    // phase 1: stage and reduce ||eta||^2 per cone
+    for (int64_t l = threadIdx.x; l < len; l += PS_THREADS) {
+      F v = in[e_lo + l];
+      if (l < PS_CAP) stage[l] = v;
+      int lo = 0, hi = nown - 1;                      // last cone c with coff[c] <= l
+      while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (coff[mid] <= l) lo = mid; else hi = mid - 1;
+      }
+      if (l != coff[lo]) atomicAdd(&sums[lo], (double)v * (double)v);
+    }
+    __syncthreads();
+    // phase 2: closed-form projection
+    for (int64_t l = threadIdx.x; l < len; l += PS_THREADS) {
+      int lo = 0, hi = nown - 1;
+      while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (coff[mid] <= l) lo = mid; else hi = mid - 1;
+      }
+      const int c0 = coff[lo];
+      const double t = (double)((c0 < PS_CAP) ? stage[c0] : in[e_lo + c0]);
+      const double a = sqrt(sums[lo]);
+      F v = (l < PS_CAP) ? stage[l] : in[e_lo + l];
+      double r;
+      if (a <= t) {
+        r = (double)v;
+      } else if (a <= -t) {
+        r = 0.0;
+      } else {
+        const double sc = 0.5 * (t + a);
+        r = (l == c0) ? sc : (sc / a) * (double)v;
+      }
+      out[e_lo + l] = (F)r;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void validate_offsets_kernel(const int64_t* off, int64_t ncones, int64_t N, int* bad) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0 && (off[0] != 0 || off[ncones] != N)) atomicOr(bad, 1);
+  if (i < ncones && off[i + 1] < off[i]) atomicOr(bad, 1);
+}
+
+}  // namespace nrto
+
+using namespace nrto;
+
+extern "C" nrto_status nrto_project_soc(const void* in, void* out, const int64_t* seg_off,
+                                        int64_t n_cones, int64_t n_entries, int32_t dtype,
+                                        int32_t flags, void* stream) {
+  if (n_cones < 0 || n_entries < 0) return set_global_error(NRTO_ERR_ARG, "negative size");
+  if (dtype != 0 && dtype != 1) return set_global_error(NRTO_ERR_ARG, "dtype must be 0 (f64) or 1 (f32)");
+  if (n_entries == 0 || n_cones == 0) return NRTO_OK;
+  if (!in || !out || !seg_off) return set_global_error(NRTO_ERR_ARG, "null pointer");
+  hipStream_t s = (hipStream_t)stream;
+  if (flags & 1) {
+    int* bad = nullptr;
+    if (hipMalloc(&bad, sizeof(int)) != hipSuccess) return set_global_error(NRTO_ERR_ALLOC, "hipMalloc failed");
+    int zero = 0, h = 0;
+    hipMemcpyAsync(bad, &zero, sizeof(int), hipMemcpyHostToDevice, s);
+    int64_t nb = (n_cones + 255) / 256;
+    validate_offsets_kernel<<<dim3((unsigned)nb), dim3(256), 0, s>>>(seg_off, n_cones, n_entries, bad);
+    hipMemcpyAsync(&h, bad, sizeof(int), hipMemcpyDeviceToHost, s);
+    hipError_t e = hipStreamSynchronize(s);
+    hipFree(bad);
+    if (e != hipSuccess) return set_global_error(NRTO_ERR_HIP, hipGetErrorString(e));
+    if (h) return set_global_error(NRTO_ERR_ARG, "seg_off must start at 0, be non-decreasing and end at n_entries");
+  }
+  int64_t nblocks = (n_entries + PS_TILE - 1) / PS_TILE;
+  if (nblocks > 0x7fffffff) return set_global_error(NRTO_ERR_ARG, "too many entries");
+  if (dtype == 0)
+    project_soc_kernel<double><<<dim3((unsigned)nblocks), dim3(PS_THREADS), 0, s>>>(
+        (const double*)in, (double*)out, seg_off, n_cones, n_entries);
+  else
+    project_soc_kernel<float><<<dim3((unsigned)nblocks), dim3(PS_THREADS), 0, s>>>(
+        (const float*)in, (float*)out, seg_off, n_cones, n_entries);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_global_error(NRTO_ERR_HIP, hipGetErrorString(e));
+  return NRTO_OK;
+}

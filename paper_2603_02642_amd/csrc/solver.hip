@@ -1,0 +1,1521 @@
+// Persistent per-instance SOCP solver for gfx950: NRTO-DR and NRTO-FullADMM.
+//
+// One workgroup owns one instance for the whole solve (all ADMM and DR
+// iterations, the (du, p) block and the KKT checks run inside one launch; no
+// host round trip per iteration).  Per iteration the hot pass streams the cone
+// entries once:
+//   forward gain GEMM   eta_j[k] = r K_k' b_{j,k} + b_hat_j[k]  (K_k from LDS)
+//   reflection / relaxation and the closed-form SOC projection (wave64
+//   reductions: one wave per long cone, packed short cones per wave)
+//   adjoint gain GEMM   R_k += b_{j,k} (.)'  accumulated with LDS atomics
+// followed by the reduced-KKT block solve K_k = G_k^-1 R_k (FP64 Cholesky of
+// the n_u x n_u blocks G_k, factored once per solve).  The (du, p) block is
+// solved exactly by wave 0: semismooth Newton on the squared-hinge form whose
+// Newton systems are LQ problems solved by a Riccati recursion, plus a
+// trust-region multiplier search.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace nrto {
+
+constexpr int EMAX = 16;
+#ifndef NRTO_SOLVER_MAX_THREADS
+#define NRTO_SOLVER_MAX_THREADS 512
+#endif  // entries per lane of a long-cone task (cones up to 1024 entries)
+
+template <typename F> __device__ __forceinline__ const F* bhat_ptr(const DevPtrs& g);
+template <> __device__ __forceinline__ const double* bhat_ptr<double>(const DevPtrs& g) { return g.bhat64; }
+template <> __device__ __forceinline__ const float* bhat_ptr<float>(const DevPtrs& g) { return g.bhat32; }
+template <typename F> __device__ __forceinline__ const F* bvec_ptr(const DevPtrs& g);
+template <> __device__ __forceinline__ const double* bvec_ptr<double>(const DevPtrs& g) { return g.bvec64; }
+template <> __device__ __forceinline__ const float* bvec_ptr<float>(const DevPtrs& g) { return g.bvec32; }
+
+__device__ __forceinline__ double atomic_load_agent(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Shared-memory carve-up for one instance workgroup.
+template <typename F>
+struct Smem {
+  F* Kf;        // NU*T*NX, u-major: Kf[(u*T + k)*NX + x]
+  F* Racc;      // NU*T*NX, same layout
+  double* Gl;   // T*NU*NU Cholesky factors
+  double* red;  // 128: [0, 64) block reductions, [64, 128) broadcast scalars
+  double* wscr; // W*128: per-wave cone sums / broadcast
+  double* qp;   // wave-0 QP scratch
+  int* ctr;     // 4 ints
+};
+
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+__host__ __device__ inline size_t qp_scratch_doubles(int nx, int nu) {
+  return 2 * nx * nx + nx + nx * nu + 2 * nu * nu + nu * nx + nu + 2 * nx + 64;
+}
+
+__host__ __device__ inline size_t smem_bytes(int T, int nx, int nu, int fbytes, int W) {
+  size_t s = 0;
+  s += align16((size_t)nu * T * nx * fbytes);
+  s += align16((size_t)nu * T * nx * fbytes);
+  s += align16((size_t)T * nu * nu * 8);
+  s += align16(128 * 8);
+  s += align16((size_t)W * 128 * 8);
+  s += align16(qp_scratch_doubles(nx, nu) * 8);
+  s += 16;
+  return s;
+}
+
+template <typename F>
+__device__ Smem<F> carve(char* base, int T, int nx, int nu, int W) {
+  Smem<F> m;
+  size_t o = 0;
+  m.Kf = (F*)(base + o); o += align16((size_t)nu * T * nx * sizeof(F));
+  m.Racc = (F*)(base + o); o += align16((size_t)nu * T * nx * sizeof(F));
+  m.Gl = (double*)(base + o); o += align16((size_t)T * nu * nu * 8);
+  m.red = (double*)(base + o); o += align16(128 * 8);
+  m.wscr = (double*)(base + o); o += align16((size_t)W * 128 * 8);
+  m.qp = (double*)(base + o); o += align16(qp_scratch_doubles(nx, nu) * 8);
+  m.ctr = (int*)(base + o);
+  return m;
+}
+
+// Block-wide sum of up to 4 values per thread (deterministic order).
+template <int NV>
+__device__ void block_sum(double* red, double (&v)[NV], int W) {
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+  __syncthreads();
+  if (lane_id() == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) red[wave_id() * 4 + i] = v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double s = 0.0;
+    for (int w = 0; w < W; ++w) s += red[w * 4 + i];
+    v[i] = s;
+  }
+  __syncthreads();
+}
+
+template <int NV>
+__device__ void block_max(double* red, double (&v)[NV], int W) {
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_max(v[i]);
+  __syncthreads();
+  if (lane_id() == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) red[wave_id() * 4 + i] = v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double s = red[i];
+    for (int w = 1; w < W; ++w) s = fmax(s, red[w * 4 + i]);
+    v[i] = s;
+  }
+  __syncthreads();
+}
+
+template <int NU>
+__device__ __forceinline__ void chol_inplace(double* G) {
+  // lower Cholesky of an NU x NU SPD matrix stored row-major; upper part untouched
+#pragma unroll
+  for (int j = 0; j < NU; ++j) {
+    double s = G[j * NU + j];
+#pragma unroll
+    for (int l = 0; l < j; ++l) s -= G[j * NU + l] * G[j * NU + l];
+    const double d = sqrt(fmax(s, 1e-300));
+    G[j * NU + j] = d;
+#pragma unroll
+    for (int i = j + 1; i < NU; ++i) {
+      double t = G[i * NU + j];
+#pragma unroll
+      for (int l = 0; l < j; ++l) t -= G[i * NU + l] * G[j * NU + l];
+      G[i * NU + j] = t / d;
+    }
+  }
+}
+
+template <int NU>
+__device__ __forceinline__ void chol_solve(const double* L, double (&z)[NU]) {
+#pragma unroll
+  for (int i = 0; i < NU; ++i) {
+    double t = z[i];
+#pragma unroll
+    for (int l = 0; l < i; ++l) t -= L[i * NU + l] * z[l];
+    z[i] = t / L[i * NU + i];
+  }
+#pragma unroll
+  for (int i = NU - 1; i >= 0; --i) {
+    double t = z[i];
+#pragma unroll
+    for (int l = i + 1; l < NU; ++l) t -= L[l * NU + i] * z[l];
+    z[i] = t / L[i * NU + i];
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Instance view: pointers of one instance.
+template <int NX, int NU, typename F>
+struct Inst {
+  int T, ng, nent, ntask;
+  double r, r_trust;
+  const int32_t* cm;
+  double* ca;        // carr + cone0; column stride = ncones
+  int64_t cstride;
+  const double* W;
+  const F* bhat;
+  const F* bvec;
+  F* st;
+  F* nuv;
+  const double *A, *B, *xhat, *uhat;
+  double *dx, *du, *dx2, *du2, *K, *Kt, *kscr, *ric;
+  const double *Q, *Ru, *RK2, *xg;
+  const int32_t* tls;  // state cones by time: [tls[t], tls[t+1])
+  const int32_t* tlc;  // control cones by step: [tlc[k], tlc[k+1])
+  const WaveTask* tasks;
+  const uint64_t* tmask;
+  double* mu;
+  double* iscr;
+  int32_t* flags;
+
+  __device__ double& C(int a, int j) const { return ca[(int64_t)a * cstride + j]; }
+};
+
+template <int NX, int NU, typename F>
+__device__ Inst<NX, NU, F> make_inst(const DevPtrs& g, int ii) {
+  const InstDev& d = g.inst[ii];
+  Inst<NX, NU, F> I;
+  I.T = d.T;
+  I.ng = d.ng;
+  I.nent = d.nent;
+  I.ntask = d.ntask;
+  I.r = d.radius;
+  I.r_trust = d.r_trust;
+  I.cm = g.cmeta + d.cone0 * CM_N;
+  I.ca = g.carr + d.cone0;
+  I.cstride = g.ncones;
+  I.W = g.w + d.oW;
+  I.bhat = bhat_ptr<F>(g) + d.ent0;
+  I.bvec = bvec_ptr<F>(g) + d.bv0;
+  I.st = (F*)g.st + d.ent0;
+  I.nuv = (F*)g.nu + d.ent0;
+  I.A = g.A + d.oA;
+  I.B = g.B + d.oB;
+  I.xhat = g.xhat + d.oX;
+  I.uhat = g.uhat + d.oU;
+  I.dx = g.dx + d.oX;
+  I.du = g.du + d.oU;
+  I.dx2 = g.dx2 + d.oX;
+  I.du2 = g.du2 + d.oU;
+  I.K = g.K + d.oK;
+  I.Kt = g.Kt + d.oK;
+  I.kscr = g.kscr + d.oK;
+  I.ric = g.ric + d.oR;
+  const double* prm = g.prm + d.oP;
+  ParamOffsets po = param_offsets(NX, NU, d.n_obs);
+  I.Q = prm + po.Q;
+  I.Ru = prm + po.Ru;
+  I.RK2 = prm + po.RK2;
+  I.xg = prm + po.xg;
+  I.tls = g.tl + d.oTL;
+  I.tlc = I.tls + (d.T + 2);
+  I.tasks = g.tasks + d.task0;
+  I.tmask = g.tmask + d.task0;
+  I.mu = g.mu + ii;
+  I.iscr = g.iscr + (int64_t)ii * ISCR_N;
+  I.flags = g.flags + (int64_t)ii * 4;
+  return I;
+}
+
+// Linear part a_j(du, dx) of constraint j: w_j' dx_{t_j} (state) or s du_{k,i} (control).
+template <int NX, int NU, typename F>
+__device__ __forceinline__ double cons_lin(const Inst<NX, NU, F>& I, int j, const double* dx, const double* du) {
+  const int32_t* m = I.cm + j * CM_N;
+  if (m[CM_KIND] == 0) {
+    const double* w = I.W + (int64_t)j * NX;
+    const double* x = dx + (int64_t)m[CM_TIME] * NX;
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < NX; ++i) s += w[i] * x[i];
+    return s;
+  }
+  return (double)m[CM_CSIGN] * du[(int64_t)m[CM_TIME] * NU + m[CM_CIDX]];
+}
+
+// ----------------------------------------------------------------------------
+// Factor: G_k = 2 RK2 + shift I + coef sum_j b_jk b_jk'  -> Cholesky in LDS.
+template <int NX, int NU, typename F>
+__device__ void factor_blocks(const Inst<NX, NU, F>& I, Smem<F>& S, double coef, double shift) {
+  const int T = I.T;
+  for (int i = threadIdx.x; i < T * NU * NU; i += blockDim.x) S.Gl[i] = 0.0;
+  __syncthreads();
+  for (int j = threadIdx.x; j < I.ng; j += blockDim.x) {
+    const int32_t* m = I.cm + j * CM_N;
+    const int k0 = m[CM_K0], nb = m[CM_NBLK], bo = m[CM_BOFF];
+    for (int b = 0; b < nb; ++b) {
+      if (k0 + b >= T) break;
+      const F* bv = I.bvec + (int64_t)(bo + b) * NU;
+      double v[NU];
+#pragma unroll
+      for (int u = 0; u < NU; ++u) v[u] = (double)bv[u];
+      double* G = S.Gl + (k0 + b) * NU * NU;
+#pragma unroll
+      for (int u = 0; u < NU; ++u)
+#pragma unroll
+        for (int w = 0; w <= u; ++w)
+          if (v[u] * v[w] != 0.0) atomicAdd(&G[u * NU + w], v[u] * v[w]);
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < T; k += blockDim.x) {
+    double* G = S.Gl + k * NU * NU;
+#pragma unroll
+    for (int u = 0; u < NU; ++u)
+#pragma unroll
+      for (int w = 0; w <= u; ++w)
+        G[u * NU + w] = coef * G[u * NU + w] + 2.0 * I.RK2[u * NU + w] + (u == w ? shift : 0.0);
+    chol_inplace<NU>(G);
+  }
+  __syncthreads();
+}
+
+// K-solve.  DR: K = G^-1 (sigma_chi K~ + sigma_s r Racc), K~ += alpha (K - K~).
+// FullADMM: K = G'^-1 (2 RK2 K + rho r Racc).  Racc is zeroed; Kf mirrors K.
+template <int NX, int NU, typename F, int METHOD>
+__device__ void k_solve(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o) {
+  const int T = I.T;
+  for (int col = threadIdx.x; col < T * NX; col += blockDim.x) {
+    const int k = col / NX, x = col - k * NX;
+    double z[NU];
+    if (METHOD == NRTO_DR) {
+      const double a = o.sigma_s * I.r;
+#pragma unroll
+      for (int u = 0; u < NU; ++u)
+        z[u] = o.sigma_chi * I.Kt[(k * NU + u) * NX + x] + a * (double)S.Racc[(u * T + k) * NX + x];
+    } else {
+      const double a = o.rho * I.r;
+      double kp[NU];
+#pragma unroll
+      for (int u = 0; u < NU; ++u) kp[u] = I.K[(k * NU + u) * NX + x];
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < NU; ++w) s += I.RK2[u * NU + w] * kp[w];
+        z[u] = 2.0 * s + a * (double)S.Racc[(u * T + k) * NX + x];
+      }
+    }
+    chol_solve<NU>(S.Gl + k * NU * NU, z);
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      I.K[(k * NU + u) * NX + x] = z[u];
+      S.Kf[(u * T + k) * NX + x] = (F)z[u];
+      S.Racc[(u * T + k) * NX + x] = (F)0;
+      if (METHOD == NRTO_DR) {
+        double kt = I.Kt[(k * NU + u) * NX + x];
+        I.Kt[(k * NU + u) * NX + x] = kt + o.alpha * (z[u] - kt);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Load K (double, global) into Kf and zero Racc.
+template <int NX, int NU, typename F>
+__device__ void load_kf(const Inst<NX, NU, F>& I, Smem<F>& S) {
+  const int T = I.T;
+  for (int i = threadIdx.x; i < T * NU * NX; i += blockDim.x) {
+    const int k = i / (NU * NX), rem = i - k * NU * NX, u = rem / NX, x = rem - u * NX;
+    S.Kf[(u * T + k) * NX + x] = (F)I.K[i];
+    S.Racc[(u * T + k) * NX + x] = (F)0;
+  }
+  __syncthreads();
+}
+
+// ----------------------------------------------------------------------------
+// Task iteration helpers.
+struct EntryPos {
+  int c;    // cone (local)
+  int le;   // index inside the cone (0 = t slot)
+};
+
+__device__ __forceinline__ int next_task(int* ctr) {
+  int t = 0;
+  if (lane_id() == 0) t = atomicAdd(ctr, 1);
+  return __shfl(t, 0, NRTO_WAVE);
+}
+
+// Per-entry geometry of an eta entry: block time k, component x, block index.
+template <int NX>
+__device__ __forceinline__ void entry_block(const int32_t* m, int le, int& k, int& x, int& b) {
+  const int m1 = le - 1;
+  const int blk = m1 / NX;
+  x = m1 - blk * NX;
+  k = m[CM_K0] + blk;
+  b = m[CM_BOFF] + blk;
+}
+
+template <int NX, int NU, typename F>
+__device__ __forceinline__ F fwd_gemm(const Inst<NX, NU, F>& I, const Smem<F>& S, int T, int k, int x,
+                                      const F* bv) {
+  F f = (F)0;
+  if (k >= T) return f;   // last block of a state constraint at t = T: b = 0, no gain
+#pragma unroll
+  for (int u = 0; u < NU; ++u) f += bv[u] * S.Kf[(u * T + k) * NX + x];
+  return f;
+}
+
+template <int NX, int NU, typename F>
+__device__ __forceinline__ void adj_gemm(Smem<F>& S, int T, int k, int x, const F* bv, F v) {
+  if (k >= T) return;
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const F c = bv[u] * v;
+    if (c != (F)0) atomicAdd(&S.Racc[(u * T + k) * NX + x], c);
+  }
+}
+
+// Closed-form projection scale: returns (t_hat, eta scale) for input (t, a = ||eta||).
+__device__ __forceinline__ void soc_case(double t, double a, double& that, double& scale) {
+  if (a <= t) {
+    that = t;
+    scale = 1.0;
+  } else if (a <= -t) {
+    that = 0.0;
+    scale = 0.0;
+  } else {
+    that = 0.5 * (t + a);
+    scale = that / a;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// DR pass: one relaxed DR iteration over all cones of the instance (after the
+// K-solve).  Accumulates sum ||delta s~||^2 and ||s~||^2.
+template <int NX, int NU, typename F>
+__device__ void dr_pass(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o, double (&acc)[2]) {
+  const int T = I.T;
+  const int lane = lane_id();
+  const F r = (F)I.r;
+  const double al = o.alpha;
+  const double den = o.rho + o.sigma_chi + o.sigma_s;
+  double* ws = S.wscr + wave_id() * 128;
+  for (int t = next_task(S.ctr); t < I.ntask; t = next_task(S.ctr)) {
+    const WaveTask tk = I.tasks[t];
+    if (tk.ncone == 1 && tk.len > NRTO_WAVE) {
+      // one long cone, EMAX entries per lane
+      const int c = tk.cone;
+      const int32_t* m = I.cm + c * CM_N;
+      F sv[EMAX], tv[EMAX], hv[EMAX];
+      double sq = 0.0, ptc = 0.0;
+#pragma unroll
+      for (int i = 0; i < EMAX; ++i) {
+        const int le = lane + i * NRTO_WAVE;
+        sv[i] = tv[i] = hv[i] = (F)0;
+        if (le < tk.len) {
+          const int64_t e = tk.ebeg + le;
+          const F stv = I.st[e];
+          F s, bh;
+          if (le == 0) {
+            ptc = (o.sigma_chi * I.C(CA_PTT, c) + o.rho * I.C(CA_P, c) + I.C(CA_LAM, c) +
+                   o.sigma_s * (double)stv) / den;
+            s = (F)ptc;
+            bh = (F)0;
+          } else {
+            int k, x, b;
+            entry_block<NX>(m, le, k, x, b);
+            bh = I.bhat[e];
+            s = r * fwd_gemm<NX, NU, F>(I, S, T, k, x, I.bvec + (int64_t)b * NU) + bh;
+            const F sr = (F)2 * s - stv;
+            sq += (double)sr * (double)sr;
+          }
+          sv[i] = s;
+          tv[i] = stv;
+          hv[i] = bh;
+        }
+      }
+      const double a = sqrt(wave_sum(sq));
+      const double tref = __shfl((double)((F)2 * sv[0] - tv[0]), 0, NRTO_WAVE);
+      double that, scale;
+      soc_case(tref, a, that, scale);
+      double dsum = 0.0, nsum = 0.0;
+#pragma unroll
+      for (int i = 0; i < EMAX; ++i) {
+        const int le = lane + i * NRTO_WAVE;
+        if (le < tk.len) {
+          const int64_t e = tk.ebeg + le;
+          const F sr = (F)2 * sv[i] - tv[i];
+          const F shat = (le == 0) ? (F)that : (F)(scale * (double)sr);
+          const F diff = shat - sv[i];
+          const F stn = tv[i] + (F)al * diff;
+          I.st[e] = stn;
+          const double dd = al * (double)diff;
+          dsum += dd * dd;
+          nsum += (double)stn * (double)stn;
+          if (le == 0) {
+            I.C(CA_PT, c) = ptc;
+            const double pt0 = I.C(CA_PTT, c);
+            I.C(CA_PTT, c) = pt0 + al * (ptc - pt0);
+          } else {
+            int k, x, b;
+            entry_block<NX>(m, le, k, x, b);
+            adj_gemm<NX, NU, F>(S, T, k, x, I.bvec + (int64_t)b * NU, stn - hv[i]);
+          }
+        }
+      }
+      acc[0] += dsum;
+      acc[1] += nsum;
+    } else {
+      // packed short cones: one entry per lane
+      const uint64_t mask = I.tmask[t];
+      const int l = lane;
+      const bool valid = l < tk.len;
+      const uint64_t pre = mask & ((l == 63) ? ~0ull : ((2ull << l) - 1ull));
+      const int cl = __popcll(pre) - 1;
+      const int cs = 63 - __clzll(pre);
+      const int le = l - cs;
+      const int c = tk.cone + cl;
+      ws[l] = 0.0;
+      wave_sync();
+      F s = (F)0, stv = (F)0, bh = (F)0;
+      double ptc = 0.0;
+      int k = 0, x = 0, b = 0;
+      const int32_t* m = I.cm + c * CM_N;
+      if (valid) {
+        const int64_t e = tk.ebeg + l;
+        stv = I.st[e];
+        if (le == 0) {
+          ptc = (o.sigma_chi * I.C(CA_PTT, c) + o.rho * I.C(CA_P, c) + I.C(CA_LAM, c) +
+                 o.sigma_s * (double)stv) / den;
+          s = (F)ptc;
+          ws[64 + cl] = (double)((F)2 * s - stv);
+        } else {
+          entry_block<NX>(m, le, k, x, b);
+          bh = I.bhat[e];
+          s = r * fwd_gemm<NX, NU, F>(I, S, T, k, x, I.bvec + (int64_t)b * NU) + bh;
+          const F sr = (F)2 * s - stv;
+          atomicAdd(&ws[cl], (double)sr * (double)sr);
+        }
+      }
+      wave_sync();
+      if (valid) {
+        const int64_t e = tk.ebeg + l;
+        const double a = sqrt(ws[cl]);
+        const double tref = ws[64 + cl];
+        double that, scale;
+        soc_case(tref, a, that, scale);
+        const F sr = (F)2 * s - stv;
+        const F shat = (le == 0) ? (F)that : (F)(scale * (double)sr);
+        const F diff = shat - s;
+        const F stn = stv + (F)al * diff;
+        I.st[e] = stn;
+        const double dd = al * (double)diff;
+        acc[0] += dd * dd;
+        acc[1] += (double)stn * (double)stn;
+        if (le == 0) {
+          I.C(CA_PT, c) = ptc;
+          const double pt0 = I.C(CA_PTT, c);
+          I.C(CA_PTT, c) = pt0 + al * (ptc - pt0);
+        } else {
+          adj_gemm<NX, NU, F>(S, T, k, x, I.bvec + (int64_t)b * NU, stn - bh);
+        }
+      }
+      wave_sync();
+    }
+  }
+}
+
+// R pass: Racc = sum_j b_jk (s~_eta - b_hat)' from the current DR state.
+template <int NX, int NU, typename F>
+__device__ void r_pass(const Inst<NX, NU, F>& I, Smem<F>& S) {
+  const int T = I.T;
+  for (int t = next_task(S.ctr); t < I.ntask; t = next_task(S.ctr)) {
+    const WaveTask tk = I.tasks[t];
+    // lane -> entries of the task; the cone of each entry by scanning cone offsets
+    int c = tk.cone;
+    for (int le0 = lane_id(); le0 < tk.len; le0 += NRTO_WAVE) {
+      const int eloc = tk.ebeg + le0;
+      while (c + 1 < tk.cone + tk.ncone && I.cm[(c + 1) * CM_N + CM_EOFF] <= eloc) ++c;
+      const int32_t* m = I.cm + c * CM_N;
+      const int le = eloc - m[CM_EOFF];
+      if (le == 0) continue;
+      int k, x, b;
+      entry_block<NX>(m, le, k, x, b);
+      adj_gemm<NX, NU, F>(S, T, k, x, I.bvec + (int64_t)b * NU, I.st[eloc] - I.bhat[eloc]);
+    }
+  }
+}
+
+// FullADMM pass: (deferred) lambda_nu update with the current K, Block 1
+// projection, adjoint accumulation of nu - b_hat.  acc: [r_nu^2 (previous
+// iteration), r_d^2 / rho^2].
+template <int NX, int NU, typename F>
+__device__ void fa_pass(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o, bool pending,
+                        double (&acc)[2]) {
+  const int T = I.T;
+  const int lane = lane_id();
+  const F r = (F)I.r;
+  double* ws = S.wscr + wave_id() * 128;
+  for (int t = next_task(S.ctr); t < I.ntask; t = next_task(S.ctr)) {
+    const WaveTask tk = I.tasks[t];
+    if (tk.ncone == 1 && tk.len > NRTO_WAVE) {
+      const int c = tk.cone;
+      const int32_t* m = I.cm + c * CM_N;
+      F yv[EMAX], lv[EMAX];
+      double sq = 0.0, rn = 0.0, yt = 0.0;
+#pragma unroll
+      for (int i = 0; i < EMAX; ++i) {
+        const int le = lane + i * NRTO_WAVE;
+        yv[i] = lv[i] = (F)0;
+        if (le < tk.len) {
+          const int64_t e = tk.ebeg + le;
+          if (le == 0) {
+            yt = I.C(CA_P, c) + I.C(CA_LAM, c);
+            yv[i] = (F)yt;
+          } else {
+            int k, x, b;
+            entry_block<NX>(m, le, k, x, b);
+            const F a = r * fwd_gemm<NX, NU, F>(I, S, T, k, x, I.bvec + (int64_t)b * NU) + I.bhat[e];
+            F l = I.st[e];
+            if (pending) {
+              const F dn = a - I.nuv[e];
+              l += dn;
+              rn += (double)dn * (double)dn;
+            }
+            lv[i] = l;
+            yv[i] = a + l;
+            sq += (double)yv[i] * (double)yv[i];
+          }
+        }
+      }
+      const double an = sqrt(wave_sum(sq));
+      const double tref = __shfl((double)yv[0], 0, NRTO_WAVE);
+      double that, scale;
+      soc_case(tref, an, that, scale);
+#pragma unroll
+      for (int i = 0; i < EMAX; ++i) {
+        const int le = lane + i * NRTO_WAVE;
+        if (le < tk.len) {
+          const int64_t e = tk.ebeg + le;
+          if (le == 0) {
+            const double old = I.C(CA_PT, c);
+            acc[1] += (that - old) * (that - old);
+            I.C(CA_PT, c) = that;
+          } else {
+            const F nv = (F)(scale * (double)yv[i]);
+            I.st[e] = lv[i];
+            I.nuv[e] = nv;
+            int k, x, b;
+            entry_block<NX>(m, le, k, x, b);
+            adj_gemm<NX, NU, F>(S, T, k, x, I.bvec + (int64_t)b * NU, nv - I.bhat[e]);
+          }
+        }
+      }
+      acc[0] += rn;
+    } else {
+      const uint64_t mask = I.tmask[t];
+      const int l = lane;
+      const bool valid = l < tk.len;
+      const uint64_t pre = mask & ((l == 63) ? ~0ull : ((2ull << l) - 1ull));
+      const int cl = __popcll(pre) - 1;
+      const int cs = 63 - __clzll(pre);
+      const int le = l - cs;
+      const int c = tk.cone + cl;
+      ws[l] = 0.0;
+      wave_sync();
+      F y = (F)0, lvv = (F)0;
+      int k = 0, x = 0, b = 0;
+      const int32_t* m = I.cm + c * CM_N;
+      if (valid) {
+        const int64_t e = tk.ebeg + l;
+        if (le == 0) {
+          const double yt = I.C(CA_P, c) + I.C(CA_LAM, c);
+          y = (F)yt;
+          ws[64 + cl] = yt;
+        } else {
+          entry_block<NX>(m, le, k, x, b);
+          const F a = r * fwd_gemm<NX, NU, F>(I, S, T, k, x, I.bvec + (int64_t)b * NU) + I.bhat[e];
+          lvv = I.st[e];
+          if (pending) {
+            const F dn = a - I.nuv[e];
+            lvv += dn;
+            acc[0] += (double)dn * (double)dn;
+          }
+          y = a + lvv;
+          atomicAdd(&ws[cl], (double)y * (double)y);
+        }
+      }
+      wave_sync();
+      if (valid) {
+        const int64_t e = tk.ebeg + l;
+        double that, scale;
+        soc_case(ws[64 + cl], sqrt(ws[cl]), that, scale);
+        if (le == 0) {
+          const double old = I.C(CA_PT, c);
+          acc[1] += (that - old) * (that - old);
+          I.C(CA_PT, c) = that;
+        } else {
+          const F nv = (F)(scale * (double)y);
+          I.st[e] = lvv;
+          I.nuv[e] = nv;
+          adj_gemm<NX, NU, F>(S, T, k, x, I.bvec + (int64_t)b * NU, nv - I.bhat[e]);
+        }
+      }
+      wave_sync();
+    }
+  }
+}
+
+// Commit the deferred FullADMM dual update lambda_nu += A_hat k_v + b_hat - nu.
+template <int NX, int NU, typename F>
+__device__ void fa_commit(const Inst<NX, NU, F>& I, Smem<F>& S) {
+  const int T = I.T;
+  const F r = (F)I.r;
+  for (int t = next_task(S.ctr); t < I.ntask; t = next_task(S.ctr)) {
+    const WaveTask tk = I.tasks[t];
+    int c = tk.cone;
+    for (int le0 = lane_id(); le0 < tk.len; le0 += NRTO_WAVE) {
+      const int eloc = tk.ebeg + le0;
+      while (c + 1 < tk.cone + tk.ncone && I.cm[(c + 1) * CM_N + CM_EOFF] <= eloc) ++c;
+      const int32_t* m = I.cm + c * CM_N;
+      const int le = eloc - m[CM_EOFF];
+      if (le == 0) continue;
+      int k, x, b;
+      entry_block<NX>(m, le, k, x, b);
+      const F a = r * fwd_gemm<NX, NU, F>(I, S, T, k, x, I.bvec + (int64_t)b * NU) + I.bhat[eloc];
+      I.st[eloc] = I.st[eloc] + (a - I.nuv[eloc]);
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// (du, p) block on wave 0.
+template <int NX, int NU>
+struct QPScratch {
+  double *V, *v, *PA, *PB, *Huu, *Hux, *hu, *L, *tmp, *red;
+};
+
+template <int NX, int NU>
+__device__ QPScratch<NX, NU> qp_carve(double* q) {
+  QPScratch<NX, NU> s;
+  s.V = q; q += NX * NX;
+  s.v = q; q += NX;
+  s.PA = q; q += NX * NX;
+  s.PB = q; q += NX * NU;
+  s.Huu = q; q += NU * NU;
+  s.Hux = q; q += NU * NX;
+  s.hu = q; q += NU;
+  s.L = q; q += NU * NU;
+  s.tmp = q; q += 2 * NX;
+  s.red = q;
+  return s;
+}
+
+// Add the active state-constraint terms of time t to (V, v): rho w w', rho beta w.
+template <int NX, int NU, typename F>
+__device__ void add_state_terms(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, int t, double rho) {
+  const int lane = lane_id();
+  const int c0 = I.tls[t], c1 = I.tls[t + 1];
+  for (int c = c0; c < c1; ++c) {
+    if (I.C(CA_ACT, c) == 0.0) continue;
+    const double* w = I.W + (int64_t)c * NX;
+    const double be = I.C(CA_BETA, c);
+    for (int idx = lane; idx < NX * NX; idx += NRTO_WAVE) {
+      const int i = idx / NX, j = idx - i * NX;
+      q.V[idx] += rho * w[i] * w[j];
+    }
+    if (lane < NX) q.v[lane] += rho * be * w[lane];
+  }
+}
+
+// Riccati solve of the LQ problem of the current active set at multiplier mu;
+// result in (du2, dx2).
+template <int NX, int NU, typename F>
+__device__ void riccati(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double rho, double mu) {
+  const int lane = lane_id();
+  const int T = I.T;
+  // terminal cost-to-go
+  for (int idx = lane; idx < NX * NX; idx += NRTO_WAVE) {
+    const int i = idx / NX, j = idx - i * NX;
+    q.V[idx] = 2.0 * I.Q[idx] + (i == j ? mu : 0.0);
+  }
+  if (lane < NX) {
+    double s = 0.0;
+    for (int j = 0; j < NX; ++j) s += I.Q[lane * NX + j] * (I.xhat[T * NX + j] - I.xg[j]);
+    q.v[lane] = 2.0 * s;
+  }
+  wave_sync();
+  add_state_terms<NX, NU, F>(I, q, T, rho);
+  wave_sync();
+  for (int k = T - 1; k >= 0; --k) {
+    const double* A = I.A + (int64_t)k * NX * NX;
+    const double* B = I.B + (int64_t)k * NX * NU;
+    for (int idx = lane; idx < NX * NX; idx += NRTO_WAVE) {
+      const int i = idx / NX, j = idx - i * NX;
+      double s = 0.0;
+#pragma unroll
+      for (int l = 0; l < NX; ++l) s += q.V[i * NX + l] * A[l * NX + j];
+      q.PA[idx] = s;
+    }
+    for (int idx = lane; idx < NX * NU; idx += NRTO_WAVE) {
+      const int i = idx / NU, u = idx - i * NU;
+      double s = 0.0;
+#pragma unroll
+      for (int l = 0; l < NX; ++l) s += q.V[i * NX + l] * B[l * NU + u];
+      q.PB[idx] = s;
+    }
+    wave_sync();
+    for (int idx = lane; idx < NU * NU; idx += NRTO_WAVE) {
+      const int u = idx / NU, w = idx - u * NU;
+      double s = 2.0 * I.Ru[idx];
+#pragma unroll
+      for (int i = 0; i < NX; ++i) s += B[i * NU + u] * q.PB[i * NU + w];
+      q.Huu[idx] = s;
+    }
+    for (int idx = lane; idx < NU * NX; idx += NRTO_WAVE) {
+      const int u = idx / NX, j = idx - u * NX;
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < NX; ++i) s += B[i * NU + u] * q.PA[i * NX + j];
+      q.Hux[idx] = s;
+    }
+    if (lane < NU) {
+      double s = 0.0;
+#pragma unroll
+      for (int w = 0; w < NU; ++w) s += I.Ru[lane * NU + w] * I.uhat[k * NU + w];
+      s *= 2.0;
+#pragma unroll
+      for (int i = 0; i < NX; ++i) s += B[i * NU + lane] * q.v[i];
+      q.hu[lane] = s;
+    }
+    wave_sync();
+    if (lane == 0) {
+      for (int c = I.tlc[k]; c < I.tlc[k + 1]; ++c) {
+        if (I.C(CA_ACT, c) == 0.0) continue;
+        const int32_t* m = I.cm + c * CM_N;
+        const int i = m[CM_CIDX];
+        q.Huu[i * NU + i] += rho;
+        q.hu[i] += rho * I.C(CA_BETA, c) * (double)m[CM_CSIGN];
+      }
+      for (int i = 0; i < NU * NU; ++i) q.L[i] = q.Huu[i];
+      chol_inplace<NU>(q.L);
+    }
+    wave_sync();
+    double* gk = I.ric + (int64_t)k * NU * (NX + 1);
+    if (lane <= NX) {
+      double z[NU];
+#pragma unroll
+      for (int u = 0; u < NU; ++u) z[u] = (lane < NX) ? q.Hux[u * NX + lane] : q.hu[u];
+      chol_solve<NU>(q.L, z);
+#pragma unroll
+      for (int u = 0; u < NU; ++u) gk[u * (NX + 1) + lane] = -z[u];
+    }
+    wave_sync();
+    if (k > 0) {
+      double nv[(NX * NX + NRTO_WAVE - 1) / NRTO_WAVE];
+      int n = 0;
+      for (int idx = lane; idx < NX * NX; idx += NRTO_WAVE, ++n) {
+        const int i = idx / NX, j = idx - i * NX;
+        double s = 2.0 * I.Q[idx] + (i == j ? mu : 0.0);
+#pragma unroll
+        for (int l = 0; l < NX; ++l) s += A[l * NX + i] * q.PA[l * NX + j];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) s += q.Hux[u * NX + i] * gk[u * (NX + 1) + j];
+        nv[n] = s;
+      }
+      double vv = 0.0;
+      if (lane < NX) {
+        double s = 0.0;
+        for (int j = 0; j < NX; ++j) s += I.Q[lane * NX + j] * (I.xhat[k * NX + j] - I.xg[j]);
+        s *= 2.0;
+#pragma unroll
+        for (int l = 0; l < NX; ++l) s += A[l * NX + lane] * q.v[l];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) s += q.Hux[u * NX + lane] * gk[u * (NX + 1) + NX];
+        vv = s;
+      }
+      wave_sync();
+      n = 0;
+      for (int idx = lane; idx < NX * NX; idx += NRTO_WAVE, ++n) q.PA[idx] = nv[n];
+      if (lane < NX) q.v[lane] = vv;
+      wave_sync();
+      for (int idx = lane; idx < NX * NX; idx += NRTO_WAVE) {
+        const int i = idx / NX, j = idx - i * NX;
+        q.V[idx] = 0.5 * (q.PA[i * NX + j] + q.PA[j * NX + i]);
+      }
+      wave_sync();
+      add_state_terms<NX, NU, F>(I, q, k, rho);
+      wave_sync();
+    }
+  }
+  // forward rollout from dx_0 = 0
+  if (lane < NX) I.dx2[lane] = 0.0;
+  wave_sync();
+  for (int k = 0; k < T; ++k) {
+    const double* gk = I.ric + (int64_t)k * NU * (NX + 1);
+    const double* xk = I.dx2 + (int64_t)k * NX;
+    if (lane < NU) {
+      double s = gk[lane * (NX + 1) + NX];
+#pragma unroll
+      for (int j = 0; j < NX; ++j) s += gk[lane * (NX + 1) + j] * xk[j];
+      I.du2[k * NU + lane] = s;
+    }
+    wave_sync();
+    if (lane < NX) {
+      const double* A = I.A + (int64_t)k * NX * NX;
+      const double* B = I.B + (int64_t)k * NX * NU;
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < NX; ++j) s += A[lane * NX + j] * xk[j];
+#pragma unroll
+      for (int u = 0; u < NU; ++u) s += B[lane * NU + u] * I.du2[k * NU + u];
+      I.dx2[(k + 1) * NX + lane] = s;
+    }
+    wave_sync();
+  }
+}
+
+// Set CA_ACT from the iterate (du, dx); returns the number of flags that changed.
+template <int NX, int NU, typename F>
+__device__ int set_active(const Inst<NX, NU, F>& I, const double* dx, const double* du) {
+  int changed = 0;
+  for (int c = lane_id(); c < I.ng; c += NRTO_WAVE) {
+    const double a = I.C(CA_BETA, c) + cons_lin<NX, NU, F>(I, c, dx, du);
+    const double f = a > 0.0 ? 1.0 : 0.0;
+    if (f != I.C(CA_ACT, c)) ++changed;
+    I.C(CA_ACT, c) = f;
+  }
+  wave_sync();
+  return (int)wave_sum((double)changed);
+}
+
+// Exact line search along (du2 - du, dx2 - dx) for the squared-hinge objective.
+template <int NX, int NU, typename F>
+__device__ double line_search(const Inst<NX, NU, F>& I, double rho, double mu) {
+  const int lane = lane_id();
+  const int T = I.T;
+  double dHd = 0.0, gd = 0.0;
+  for (int idx = lane; idx < T * NU; idx += NRTO_WAVE) {
+    const int k = idx / NU, u = idx - k * NU;
+    double hd = 0.0, hg = 0.0;
+#pragma unroll
+    for (int w = 0; w < NU; ++w) {
+      const double dw = I.du2[k * NU + w] - I.du[k * NU + w];
+      hd += I.Ru[u * NU + w] * dw;
+      hg += I.Ru[u * NU + w] * (I.uhat[k * NU + w] + I.du[k * NU + w]);
+    }
+    const double du_ = I.du2[idx] - I.du[idx];
+    dHd += 2.0 * hd * du_;
+    gd += 2.0 * hg * du_;
+  }
+  for (int idx = lane; idx < T * NX; idx += NRTO_WAVE) {
+    const int t = idx / NX + 1, i = idx - (t - 1) * NX;
+    double hd = 0.0, hg = 0.0;
+#pragma unroll
+    for (int j = 0; j < NX; ++j) {
+      const double dj = I.dx2[t * NX + j] - I.dx[t * NX + j];
+      hd += I.Q[i * NX + j] * dj;
+      hg += I.Q[i * NX + j] * (I.xhat[t * NX + j] - I.xg[j] + I.dx[t * NX + j]);
+    }
+    const double di = I.dx2[t * NX + i] - I.dx[t * NX + i];
+    dHd += (2.0 * hd + mu * di) * di;
+    gd += (2.0 * hg + mu * I.dx[t * NX + i]) * di;
+  }
+  dHd = wave_sum(dHd);
+  gd = wave_sum(gd);
+  for (int c = lane; c < I.ng; c += NRTO_WAVE) {
+    const double a0 = cons_lin<NX, NU, F>(I, c, I.dx, I.du);
+    const double a1 = cons_lin<NX, NU, F>(I, c, I.dx2, I.du2);
+    I.C(CA_LA, c) = I.C(CA_BETA, c) + a0;
+    I.C(CA_LE, c) = a1 - a0;
+  }
+  wave_sync();
+  if (dHd <= 0.0) return 0.0;
+  auto deriv = [&](double s, double& slope) {
+    double f = 0.0, sl = 0.0;
+    for (int c = lane; c < I.ng; c += NRTO_WAVE) {
+      const double a = I.C(CA_LA, c), e = I.C(CA_LE, c);
+      const double z = a + s * e;
+      if (z > 0.0) {
+        f += e * z;
+        sl += e * e;
+      }
+    }
+    f = wave_sum(f);
+    sl = wave_sum(sl);
+    slope = dHd + rho * sl;
+    return s * dHd + gd + rho * f;
+  };
+  double sl0;
+  double lo = 0.0, flo = deriv(0.0, sl0);
+  if (flo >= 0.0) return 0.0;
+  double hi = 1.0, slh;
+  double fhi = deriv(hi, slh);
+  int guard = 0;
+  while (fhi < 0.0 && guard < 60) {
+    lo = hi;
+    flo = fhi;
+    sl0 = slh;
+    hi *= 2.0;
+    fhi = deriv(hi, slh);
+    ++guard;
+  }
+  if (fhi <= 0.0) return hi;
+  double s = lo;
+  for (int it = 0; it < 100; ++it) {
+    double cand = lo - flo / sl0;          // root of the linear piece to the right of lo
+    if (!(cand > lo && cand < hi)) cand = 0.5 * (lo + hi);
+    double slc;
+    const double fc = deriv(cand, slc);
+    s = cand;
+    if (fc == 0.0) break;
+    if (fc < 0.0) {
+      lo = cand;
+      flo = fc;
+      sl0 = slc;
+    } else {
+      hi = cand;
+    }
+    if (hi - lo <= 1e-15 * hi) {
+      s = hi;
+      break;
+    }
+    // the piece at lo reaches exactly zero inside (lo, hi): Newton lands on the root next
+  }
+  return s;
+}
+
+// Semismooth Newton at fixed mu from the current iterate (du, dx).
+template <int NX, int NU, typename F>
+__device__ int ssn(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double rho, double mu) {
+  const int T = I.T;
+  const int lane = lane_id();
+  set_active<NX, NU, F>(I, I.dx, I.du);
+  int solves = 0;
+  for (int it = 0; it < 60; ++it) {
+    riccati<NX, NU, F>(I, q, rho, mu);
+    ++solves;
+    // does the candidate keep the active set?
+    int changed = 0;
+    for (int c = lane; c < I.ng; c += NRTO_WAVE) {
+      const double a = I.C(CA_BETA, c) + cons_lin<NX, NU, F>(I, c, I.dx2, I.du2);
+      if ((a > 0.0 ? 1.0 : 0.0) != I.C(CA_ACT, c)) ++changed;
+    }
+    changed = (int)wave_sum((double)changed);
+    if (changed == 0) {
+      for (int i = lane; i < T * NU; i += NRTO_WAVE) I.du[i] = I.du2[i];
+      for (int i = lane; i < (T + 1) * NX; i += NRTO_WAVE) I.dx[i] = I.dx2[i];
+      wave_sync();
+      break;
+    }
+    const double s = line_search<NX, NU, F>(I, rho, mu);
+    double step = 0.0;
+    for (int i = lane; i < T * NU; i += NRTO_WAVE) {
+      const double d = s * (I.du2[i] - I.du[i]);
+      step = fmax(step, fabs(d));
+      I.du[i] += d;
+    }
+    for (int i = lane; i < (T + 1) * NX; i += NRTO_WAVE) I.dx[i] += s * (I.dx2[i] - I.dx[i]);
+    wave_sync();
+    step = wave_max(step);
+    set_active<NX, NU, F>(I, I.dx, I.du);
+    if (step == 0.0) break;
+  }
+  return solves;
+}
+
+template <int NX, int NU, typename F>
+__device__ double state_norm(const Inst<NX, NU, F>& I) {
+  double s = 0.0;
+  for (int i = lane_id(); i < (I.T + 1) * NX; i += NRTO_WAVE) s += I.dx[i] * I.dx[i];
+  return sqrt(wave_sum(s));
+}
+
+// Full (du, p) block: returns Riccati solves used.  Requires CA_BETA = g0 + c.
+template <int NX, int NU, typename F>
+__device__ void rollout_dx(const Inst<NX, NU, F>& I) {
+  const int lane = lane_id();
+  if (lane < NX) I.dx[lane] = 0.0;
+  wave_sync();
+  for (int k = 0; k < I.T; ++k) {
+    if (lane < NX) {
+      const double* A = I.A + (int64_t)k * NX * NX;
+      const double* B = I.B + (int64_t)k * NX * NU;
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < NX; ++j) s += A[lane * NX + j] * I.dx[k * NX + j];
+#pragma unroll
+      for (int u = 0; u < NU; ++u) s += B[lane * NU + u] * I.du[k * NU + u];
+      I.dx[(k + 1) * NX + lane] = s;
+    }
+    wave_sync();
+  }
+}
+
+template <int NX, int NU, typename F>
+__device__ int qp_block(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double rho) {
+  const double r = I.r_trust;
+  double mu = *I.mu;
+  rollout_dx<NX, NU, F>(I);
+  int solves = ssn<NX, NU, F>(I, q, rho, mu);
+  double psi = state_norm<NX, NU, F>(I);
+  const double tol = 1e-13 * r;
+  if (!(fabs(psi - r) <= tol) && !(mu == 0.0 && psi <= r)) {
+    double lo, hi, plo, phi;
+    if (psi <= r) {
+      hi = mu;
+      phi = psi;
+      solves += ssn<NX, NU, F>(I, q, rho, 0.0);
+      psi = state_norm<NX, NU, F>(I);
+      mu = 0.0;
+      lo = 0.0;
+      plo = psi;
+    } else {
+      lo = mu;
+      plo = psi;
+      hi = fmax(2.0 * mu, 1.0);
+      solves += ssn<NX, NU, F>(I, q, rho, hi);
+      phi = state_norm<NX, NU, F>(I);
+      int guard = 0;
+      while (phi > r && guard < 80) {
+        lo = hi;
+        plo = phi;
+        hi *= 4.0;
+        solves += ssn<NX, NU, F>(I, q, rho, hi);
+        phi = state_norm<NX, NU, F>(I);
+        ++guard;
+      }
+      mu = hi;
+      psi = phi;
+    }
+    if (!(mu == 0.0 && psi <= r)) {
+      // Illinois regula falsi on f(mu) = 1/r - 1/psi(mu), increasing in mu
+      double flo = 1.0 / r - 1.0 / plo, fhi = 1.0 / r - 1.0 / phi;
+      int side = 0;
+      for (int it = 0; it < 100 && fabs(psi - r) > tol; ++it) {
+        double m = hi - fhi * (hi - lo) / (fhi - flo);
+        if (!(m > lo && m < hi)) m = 0.5 * (lo + hi);
+        solves += ssn<NX, NU, F>(I, q, rho, m);
+        psi = state_norm<NX, NU, F>(I);
+        mu = m;
+        const double fm = 1.0 / r - 1.0 / psi;
+        if (fm < 0.0) {
+          lo = m;
+          flo = fm;
+          if (side == -1) fhi *= 0.5;
+          side = -1;
+        } else {
+          hi = m;
+          fhi = fm;
+          if (side == 1) flo *= 0.5;
+          side = 1;
+        }
+        if (hi - lo <= 1e-15 * hi) break;
+      }
+    }
+  }
+  if (lane_id() == 0) {
+    *I.mu = mu;
+    I.iscr[ISCR_PSI] = psi;
+  }
+  wave_sync();
+  return solves;
+}
+
+// ----------------------------------------------------------------------------
+// FP64 KKT residual (see the oracle's definition).  Uses K (double), the
+// multipliers CA_PI, mu, and zeta from the method state.
+template <int NX, int NU, typename F, int METHOD>
+__device__ double kkt_residual(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o, bool pending, int W) {
+  const int T = I.T;
+  const double r = I.r;
+  // zero accumulator of sum_j A_hat_j' zeta_j
+  for (int i = threadIdx.x; i < T * NU * NX; i += blockDim.x) I.kscr[i] = 0.0;
+  if (threadIdx.x == 0) *S.ctr = 0;
+  __syncthreads();
+  // entry pass: per cone ||eta||^2, ||zeta||^2, zeta.eta ; adjoint of zeta
+  for (int t = next_task(S.ctr); t < I.ntask; t = next_task(S.ctr)) {
+    const WaveTask tk = I.tasks[t];
+    for (int c = tk.cone; c < tk.cone + tk.ncone; ++c) {
+      const int32_t* m = I.cm + c * CM_N;
+      const int e0 = m[CM_EOFF];
+      const int len = 1 + m[CM_NBLK] * NX;
+      double n2 = 0.0, z2 = 0.0, ze = 0.0;
+      for (int le = 1 + lane_id(); le < len; le += NRTO_WAVE) {
+        const int e = e0 + le;
+        int k, x, b;
+        entry_block<NX>(m, le, k, x, b);
+        const F* bv = I.bvec + (int64_t)b * NU;
+        double f = 0.0;
+        if (k < T) {
+#pragma unroll
+          for (int u = 0; u < NU; ++u) f += (double)bv[u] * I.K[(k * NU + u) * NX + x];
+        }
+        const double eta = r * f + (double)I.bhat[e];
+        double z;
+        if (METHOD == NRTO_DR) {
+          z = o.sigma_s * ((double)I.st[e] - eta);
+        } else {
+          double lv = (double)I.st[e];
+          if (pending) lv += eta - (double)I.nuv[e];
+          z = -o.rho * lv;
+        }
+        n2 += eta * eta;
+        z2 += z * z;
+        ze += z * eta;
+        if (k < T) {
+#pragma unroll
+          for (int u = 0; u < NU; ++u) {
+            const double cz = r * (double)bv[u] * z;
+            if (cz != 0.0) unsafeAtomicAdd(&I.kscr[(k * NU + u) * NX + x], cz);
+          }
+        }
+      }
+      n2 = wave_sum(n2);
+      z2 = wave_sum(z2);
+      ze = wave_sum(ze);
+      if (lane_id() == 0) {
+        I.C(CA_N, c) = sqrt(n2);
+        I.C(CA_ZZ, c) = z2;
+        I.C(CA_ZE, c) = ze;
+      }
+    }
+  }
+  __syncthreads();
+  // per-cone terms
+  double mx[4] = {0.0, 0.0, 0.0, 0.0};   // T3 num, T5 num, T6 num, T7 num
+  double nm[4] = {0.0, 0.0, 0.0, 0.0};   // max|g0|, max|b'du|, max n, max pi
+  double nm2[4] = {0.0, 0.0, 0.0, 0.0};  // max|e|, max pi*n, T8 num, max|p|,|pt|
+  for (int c = threadIdx.x; c < I.ng; c += blockDim.x) {
+    const double g0 = I.C(CA_G0, c);
+    const double bdu = cons_lin<NX, NU, F>(I, c, I.dx, I.du);
+    const double e = g0 + bdu;
+    const double n = I.C(CA_N, c);
+    const double pi = I.C(CA_PI, c);
+    const double zz = sqrt(I.C(CA_ZZ, c));
+    const double ze = I.C(CA_ZE, c);
+    const double p = I.C(CA_P, c), pt = I.C(CA_PT, c);
+    I.C(CA_E, c) = e;
+    const double viol = e + n;
+    mx[0] = fmax(mx[0], viol);
+    mx[1] = fmax(mx[1], fabs(p - pt));
+    mx[2] = fmax(mx[2], fabs(fmin(pi, -viol)));
+    mx[3] = fmax(mx[3], fmax(-pi, zz - pi));
+    nm[0] = fmax(nm[0], fabs(g0));
+    nm[1] = fmax(nm[1], fabs(bdu));
+    nm[2] = fmax(nm[2], n);
+    nm[3] = fmax(nm[3], pi);
+    nm2[0] = fmax(nm2[0], fabs(e));
+    nm2[1] = fmax(nm2[1], pi * n);
+    nm2[2] = fmax(nm2[2], fabs(pi * n + ze));
+    nm2[3] = fmax(nm2[3], fmax(fabs(p), fabs(pt)));
+  }
+  // T2: Q_v k - sum A_hat' zeta
+  double t2[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < T * NU * NX; i += blockDim.x) {
+    const int k = i / (NU * NX), rem = i - k * NU * NX, u = rem / NX, x = rem - u * NX;
+    double qk = 0.0;
+#pragma unroll
+    for (int w = 0; w < NU; ++w) qk += I.RK2[u * NU + w] * I.K[(k * NU + w) * NX + x];
+    qk *= 2.0;
+    const double az = atomic_load_agent(&I.kscr[i]);
+    t2[0] = fmax(t2[0], fabs(qk - az));
+    t2[1] = fmax(t2[1], fabs(qk));
+    t2[2] = fmax(t2[2], fabs(az));
+  }
+  block_max<4>(S.red, mx, W);
+  block_max<4>(S.red, nm, W);
+  block_max<4>(S.red, nm2, W);
+  block_max<4>(S.red, t2, W);
+  // T1 by costate recursions on wave 0
+  double t1v = 0.0;
+  if (wave_id() == 0) {
+    QPScratch<NX, NU> q = qp_carve<NX, NU>(S.qp);
+    const int lane = lane_id();
+    // lanes 0..NX-1: cost costate; NX..2NX-1: pi costate; 2NX..3NX-1: trust costate
+    const int which = lane / NX, i = lane - which * NX;
+    double lam = 0.0;
+    const double mu = *I.mu;
+    double g1m = 0.0, g2m = 0.0, g3m = 0.0, gsm = 0.0;
+    double* lv = q.PA;   // 3*NX doubles
+    for (int t = T; t >= 1; --t) {
+      // add the stage terms of time t
+      if (which < 3) {
+        double add = 0.0;
+        if (which == 0) {
+          double s = 0.0;
+          for (int j = 0; j < NX; ++j) s += I.Q[i * NX + j] * (I.xhat[t * NX + j] - I.xg[j] + I.dx[t * NX + j]);
+          add = 2.0 * s;
+        } else if (which == 1) {
+          for (int c = I.tls[t]; c < I.tls[t + 1]; ++c) add += I.C(CA_PI, c) * I.W[(int64_t)c * NX + i];
+        } else {
+          add = mu * I.dx[t * NX + i];
+        }
+        lam += add;
+        lv[which * NX + i] = lam;
+      }
+      wave_sync();
+      const int k = t - 1;
+      const double* A = I.A + (int64_t)k * NX * NX;
+      const double* B = I.B + (int64_t)k * NX * NU;
+      // gradients at step k from lambda_{k+1} = lv
+      if (lane < NU) {
+        double g1 = 0.0, g2 = 0.0, g3 = 0.0;
+#pragma unroll
+        for (int w = 0; w < NU; ++w) g1 += I.Ru[lane * NU + w] * (I.uhat[k * NU + w] + I.du[k * NU + w]);
+        g1 *= 2.0;
+#pragma unroll
+        for (int j = 0; j < NX; ++j) {
+          g1 += B[j * NU + lane] * lv[j];
+          g2 += B[j * NU + lane] * lv[NX + j];
+          g3 += B[j * NU + lane] * lv[2 * NX + j];
+        }
+        for (int c = I.tlc[k]; c < I.tlc[k + 1]; ++c) {
+          const int32_t* m = I.cm + c * CM_N;
+          if (m[CM_CIDX] == lane) g2 += I.C(CA_PI, c) * (double)m[CM_CSIGN];
+        }
+        g1m = fmax(g1m, fabs(g1));
+        g2m = fmax(g2m, fabs(g2));
+        g3m = fmax(g3m, fabs(g3));
+        gsm = fmax(gsm, fabs(g1 + g2 + g3));
+      }
+      // lambda_k = A_k' lambda_{k+1}
+      if (which < 3) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < NX; ++j) s += A[j * NX + i] * lv[which * NX + j];
+        lam = s;
+      }
+      wave_sync();
+    }
+    g1m = wave_max(g1m);
+    g2m = wave_max(g2m);
+    g3m = wave_max(g3m);
+    gsm = wave_max(gsm);
+    t1v = gsm / (1.0 + fmax(g1m, fmax(g2m, g3m)));
+    if (lane_id() == 0) S.red[64] = t1v;
+  }
+  __syncthreads();
+  t1v = S.red[64];
+  const double rt = I.r_trust;
+  const double psi = I.iscr[ISCR_PSI];
+  const double mu = *I.mu;
+  double res = t1v;
+  res = fmax(res, t2[0] / (1.0 + fmax(t2[1], t2[2])));
+  res = fmax(res, fmax(0.0, mx[0]) / (1.0 + fmax(nm[0], fmax(nm[1], nm[2]))));
+  res = fmax(res, fmax(0.0, psi - rt) / (1.0 + rt));
+  res = fmax(res, mx[1] / (1.0 + nm2[3]));
+  res = fmax(res, mx[2] / (1.0 + fmax(nm[3], fmax(nm2[0], nm[2]))));
+  res = fmax(res, fmax(0.0, mx[3]) / (1.0 + nm[3]));
+  res = fmax(res, nm2[2] / (1.0 + nm2[1]));
+  res = fmax(res, fabs(fmin(mu, rt - psi)) / (1.0 + fmax(mu, rt)));
+  __syncthreads();
+  return res;
+}
+
+// ----------------------------------------------------------------------------
+template <int NX, int NU, typename F, int METHOD>
+__device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, char* smem) {
+  Inst<NX, NU, F> I = make_inst<NX, NU, F>(g, ii);
+  const int W = blockDim.x / NRTO_WAVE;
+  Smem<F> S = carve<F>(smem, I.T, NX, NU, W);
+  const int T = I.T;
+  const double rho = o.rho;
+
+  // cold start: zero the method state
+  if (!o.warm) {
+    for (int64_t e = threadIdx.x; e < I.nent; e += blockDim.x) {
+      I.st[e] = (F)0;
+      I.nuv[e] = (F)0;
+    }
+    for (int c = threadIdx.x; c < I.ng; c += blockDim.x) {
+      I.C(CA_P, c) = 0.0;
+      I.C(CA_PT, c) = 0.0;
+      I.C(CA_PTT, c) = 0.0;
+      I.C(CA_LAM, c) = 0.0;
+      I.C(CA_PI, c) = 0.0;
+      I.C(CA_ACT, c) = 0.0;
+    }
+    for (int i = threadIdx.x; i < T * NU * NX; i += blockDim.x) {
+      I.K[i] = 0.0;
+      I.Kt[i] = 0.0;
+    }
+    for (int i = threadIdx.x; i < T * NU; i += blockDim.x) I.du[i] = 0.0;
+    for (int i = threadIdx.x; i < (T + 1) * NX; i += blockDim.x) I.dx[i] = 0.0;
+    if (threadIdx.x == 0) {
+      *I.mu = 0.0;
+      I.flags[0] = 0;
+    }
+  }
+  __syncthreads();
+  bool pending = I.flags[0] != 0;
+
+  // a1: factor the reduced KKT blocks once
+  if (METHOD == NRTO_DR)
+    factor_blocks<NX, NU, F>(I, S, o.sigma_s * I.r * I.r, o.sigma_chi);
+  else
+    factor_blocks<NX, NU, F>(I, S, rho * I.r * I.r, 0.0);
+
+  load_kf<NX, NU, F>(I, S);
+  if (METHOD == NRTO_DR) {
+    if (threadIdx.x == 0) *S.ctr = 0;
+    __syncthreads();
+    r_pass<NX, NU, F>(I, S);
+    __syncthreads();
+  }
+
+  int admm = 0, inner = 0, qpn = 0, status = NRTO_MAXITER;
+  double kkt = 1e300, rp = 0.0, rd = 0.0;
+  for (int l = 1; l <= o.max_admm; ++l) {
+    admm = l;
+    if (METHOD == NRTO_DR) {
+      // (6a) DR iterations on the {k_v, p~} block, warm-started
+      for (int i = 0; i < o.max_inner; ++i) {
+        k_solve<NX, NU, F, NRTO_DR>(I, S, o);
+        if (threadIdx.x == 0) *S.ctr = 0;
+        __syncthreads();
+        double acc[2] = {0.0, 0.0};
+        dr_pass<NX, NU, F>(I, S, o, acc);
+        block_sum<2>(S.red, acc, W);
+        ++inner;
+        const double rdr = sqrt(acc[0]);
+        if (rdr <= o.eps_dr_abs + o.eps_dr_rel * fmax(1.0, sqrt(acc[1]))) break;
+      }
+      // p~ of the last chi is in CA_PT, k_v of the last chi in K
+      for (int c = threadIdx.x; c < I.ng; c += blockDim.x)
+        I.C(CA_BETA, c) = I.C(CA_G0, c) + I.C(CA_PT, c) - I.C(CA_LAM, c) / rho;
+    } else {
+      if (threadIdx.x == 0) *S.ctr = 0;
+      __syncthreads();
+      double acc[2] = {0.0, 0.0};
+      fa_pass<NX, NU, F>(I, S, o, pending, acc);
+      pending = true;
+      block_sum<2>(S.red, acc, W);
+      rd = rho * sqrt(acc[1]);
+      for (int c = threadIdx.x; c < I.ng; c += blockDim.x)
+        I.C(CA_BETA, c) = I.C(CA_G0, c) + I.C(CA_PT, c) - I.C(CA_LAM, c);
+    }
+    __syncthreads();
+    // (du, p) block on wave 0
+    if (wave_id() == 0) {
+      QPScratch<NX, NU> q = qp_carve<NX, NU>(S.qp);
+      const int n = qp_block<NX, NU, F>(I, q, rho);
+      if (lane_id() == 0) S.red[65] = (double)n;
+    }
+    __syncthreads();
+    qpn += (int)S.red[65];
+    // p, pi from the (du, p) solution; then the FullADMM k_v step; dual updates
+    double acc2[2] = {0.0, 0.0};
+    for (int c = threadIdx.x; c < I.ng; c += blockDim.x) {
+      const double a = cons_lin<NX, NU, F>(I, c, I.dx, I.du);
+      const double g0 = I.C(CA_G0, c);
+      const double cc = I.C(CA_BETA, c) - g0;
+      const double p = fmin(cc, -(g0 + a));
+      const double pi = rho * fmax(0.0, g0 + a + cc);
+      const double pt = I.C(CA_PT, c);
+      I.C(CA_P, c) = p;
+      I.C(CA_PI, c) = pi;
+      if (METHOD == NRTO_DR) {
+        const double lam_old = I.C(CA_LAM, c);
+        I.C(CA_LAM, c) = lam_old + rho * (p - pt);
+      } else {
+        I.C(CA_LAM, c) = I.C(CA_LAM, c) + (p - pt);
+      }
+      acc2[0] += (p - pt) * (p - pt);
+    }
+    if (METHOD == NRTO_FULLADMM) k_solve<NX, NU, F, NRTO_FULLADMM>(I, S, o);
+    block_sum<2>(S.red, acc2, W);
+    rp = sqrt(acc2[0]);
+    if (o.eps_kkt > 0.0 && (l % o.check_every == 0 || l == o.max_admm)) {
+      kkt = kkt_residual<NX, NU, F, METHOD>(I, S, o, pending, W);
+      if (kkt <= o.eps_kkt) {
+        status = NRTO_OK;
+        break;
+      }
+    }
+  }
+  if (METHOD == NRTO_FULLADMM && pending) {
+    if (threadIdx.x == 0) *S.ctr = 0;
+    __syncthreads();
+    fa_commit<NX, NU, F>(I, S);
+    pending = false;
+    __syncthreads();
+  }
+  if (!(o.eps_kkt > 0.0)) kkt = kkt_residual<NX, NU, F, METHOD>(I, S, o, false, W);
+  if (threadIdx.x == 0) {
+    I.flags[0] = pending ? 1 : 0;
+    nrto_solve_report rep;
+    rep.status = status;
+    rep.admm_iters = admm;
+    rep.inner_iters = inner;
+    rep.qp_newton = qpn;
+    rep.kkt = kkt;
+    rep.r_p = rp;
+    rep.r_d = rd;
+    rep.mu = *I.mu;
+    g.rep[ii] = rep;
+  }
+}
+
+template <int NX, int NU, typename F, int METHOD>
+__global__ void __launch_bounds__(NRTO_SOLVER_MAX_THREADS) solve_kernel(DevPtrs g, SolveOpts o, const int32_t* order, int n) {
+  extern __shared__ __align__(16) char smem[];
+  const int ii = order[blockIdx.x];
+  solve_instance<NX, NU, F, METHOD>(g, o, ii, smem);
+}
+
+size_t solver_smem_bytes(int T, int nx, int nu, int precision, int threads) {
+  return smem_bytes(T, nx, nu, precision == NRTO_FP32 ? 4 : 8, threads / NRTO_WAVE);
+}
+
+template <int NX, int NU>
+static hipError_t launch_nxnu(const DevPtrs& g, const SolveOpts& o, const int32_t* order, int n, int threads,
+                              size_t smem, hipStream_t s) {
+  dim3 grid(n), block(threads);
+  if (o.precision == NRTO_FP32) {
+    if (o.method == NRTO_DR)
+      hipLaunchKernelGGL((solve_kernel<NX, NU, float, NRTO_DR>), grid, block, smem, s, g, o, order, n);
+    else
+      hipLaunchKernelGGL((solve_kernel<NX, NU, float, NRTO_FULLADMM>), grid, block, smem, s, g, o, order, n);
+  } else {
+    if (o.method == NRTO_DR)
+      hipLaunchKernelGGL((solve_kernel<NX, NU, double, NRTO_DR>), grid, block, smem, s, g, o, order, n);
+    else
+      hipLaunchKernelGGL((solve_kernel<NX, NU, double, NRTO_FULLADMM>), grid, block, smem, s, g, o, order, n);
+  }
+  return hipGetLastError();
+}
+
+// One launch per dynamics model present; `order` lists the instances of that
+// model (largest first).
+hipError_t launch_solver(const DevPtrs& g, const SolveOpts& o, int nx, const int32_t* order, int n, int threads,
+                         size_t smem, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (nx == 3) return launch_nxnu<3, 2>(g, o, order, n, threads, smem, s);
+  if (nx == 12) return launch_nxnu<12, 4>(g, o, order, n, threads, smem, s);
+  return launch_nxnu<14, 7>(g, o, order, n, threads, smem, s);
+}
+
+template <int NX, int NU>
+static hipError_t smem_attr(size_t bytes) {
+  hipError_t e;
+  e = hipFuncSetAttribute((const void*)solve_kernel<NX, NU, float, NRTO_DR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)solve_kernel<NX, NU, float, NRTO_FULLADMM>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)solve_kernel<NX, NU, double, NRTO_DR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)solve_kernel<NX, NU, double, NRTO_FULLADMM>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t set_solver_smem_limit(size_t bytes) {
+  hipError_t e = smem_attr<3, 2>(bytes);
+  if (e != hipSuccess) return e;
+  e = smem_attr<12, 4>(bytes);
+  if (e != hipSuccess) return e;
+  return smem_attr<14, 7>(bytes);
+}
+
+}  // namespace nrto

@@ -1,0 +1,258 @@
+"""ctypes binding of libnrto.so (argument marshalling only; every step of the
+solve runs in the HIP library).  Names follow include/nrto.h.
+
+Device buffers and streams come from PyTorch; host arrays are numpy float64.
+Loading fails loudly if the library has not been built (python -m
+paper_2603_02642_amd.build): there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnrto.so")
+
+NRTO_OK, NRTO_MAXITER, NRTO_INFEASIBLE, NRTO_FALLBACK_COLD = 0, 1, 2, 3
+NRTO_DR, NRTO_FULLADMM = 0, 1
+NRTO_FP64, NRTO_FP32 = 0, 1
+
+_dp = C.POINTER(C.c_double)
+
+
+class Problem(C.Structure):
+    _fields_ = [("dyn", C.c_int32), ("nx", C.c_int32), ("nu", C.c_int32), ("T", C.c_int32),
+                ("dt", C.c_double), ("radius", C.c_double), ("mass", C.c_double),
+                ("inertia", _dp), ("links", _dp), ("x0", _dp), ("xg", _dp), ("Q", _dp),
+                ("Ru", _dp), ("RK", _dp), ("n_obs", C.c_int32), ("obs", _dp),
+                ("u_lo", _dp), ("u_hi", _dp), ("x_lo", _dp), ("x_hi", _dp), ("u_init", _dp)]
+
+
+class Options(C.Structure):
+    _fields_ = [("method", C.c_int32), ("precision", C.c_int32), ("max_admm", C.c_int32),
+                ("max_inner", C.c_int32), ("check_every", C.c_int32), ("block_threads", C.c_int32),
+                ("rho", C.c_double), ("alpha", C.c_double), ("sigma_chi", C.c_double),
+                ("sigma_s", C.c_double), ("eps_dr_abs", C.c_double), ("eps_dr_rel", C.c_double),
+                ("eps_kkt", C.c_double), ("r_trust", C.c_double)]
+
+
+class SolveReport(C.Structure):
+    _fields_ = [("status", C.c_int32), ("admm_iters", C.c_int32), ("inner_iters", C.c_int32),
+                ("qp_newton", C.c_int32), ("kkt", C.c_double), ("r_p", C.c_double),
+                ("r_d", C.c_double), ("mu", C.c_double)]
+
+
+class StepReport(C.Structure):
+    _fields_ = [("accepted", C.c_int32), ("status", C.c_int32), ("merit_old", C.c_double),
+                ("merit_new", C.c_double), ("predicted", C.c_double), ("r_trust", C.c_double),
+                ("kkt", C.c_double)]
+
+
+_lib = None
+
+
+class NrtoError(RuntimeError):
+    pass
+
+
+def load() -> C.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise NrtoError(f"{LIB_PATH} is missing: build it with `python -m paper_2603_02642_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    P = C.POINTER
+    sig = {
+        "nrto_default_options": (None, [P(Options)]),
+        "nrto_project_soc": (i32, [vp, vp, vp, i64, i64, i32, i32, vp]),
+        "nrto_setup": (i32, [P(Problem), i32, P(Options), vp, P(vp)]),
+        "nrto_destroy": (None, [vp]),
+        "nrto_last_error": (C.c_char_p, [vp]),
+        "nrto_set_options": (i32, [vp, P(Options)]),
+        "nrto_instance_sizes": (i32, [vp, i32, P(C.c_int64)]),
+        "nrto_linearize": (i32, [vp]),
+        "nrto_upload_socp": (i32, [vp, i32] + [_dp] * 8),
+        "nrto_download_socp": (i32, [vp, i32] + [_dp] * 8),
+        "nrto_solve_socp": (i32, [vp, i32, P(SolveReport)]),
+        "nrto_get_solution": (i32, [vp, i32] + [_dp] * 7),
+        "nrto_get_state": (i32, [vp, i32] + [_dp] * 4),
+        "nrto_set_state": (i32, [vp, i32] + [_dp] * 9),
+        "nrto_scp_step": (i32, [vp, P(StepReport)]),
+        "nrto_get_nominal": (i32, [vp, i32, _dp, _dp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(st: int, ctx=None):
+    if st < 0:
+        msg = load().nrto_last_error(ctx)
+        raise NrtoError(f"nrto status {st}: {msg.decode() if msg else ''}")
+    return st
+
+
+def _ptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(_dp)
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    load().nrto_default_options(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def project_soc(x, seg_off, out=None, validate: bool = False, stream=None):
+    """Projection of concatenated cones (torch tensors on the GPU; float64 or
+    float32 values, int64 offsets of length n_cones + 1)."""
+    import torch
+    if out is None:
+        out = torch.empty_like(x)
+    dtype = 0 if x.dtype == torch.float64 else 1 if x.dtype == torch.float32 else -1
+    if dtype < 0:
+        raise TypeError("float64 or float32 values required")
+    if not (x.is_cuda and seg_off.is_cuda and out.is_cuda):
+        raise TypeError("device tensors required")
+    if seg_off.dtype != torch.int64:
+        raise TypeError("int64 offsets required")
+    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    _check(load().nrto_project_soc(C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()),
+                                   C.c_void_p(seg_off.data_ptr()), seg_off.numel() - 1, x.numel(),
+                                   dtype, 1 if validate else 0, C.c_void_p(s)))
+    return out
+
+
+class _ProblemHolder:
+    """Keeps the numpy arrays behind one ctypes Problem alive."""
+
+    def __init__(self, p):
+        f = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+        self.arrays = dict(x0=f(p.x0), xg=f(p.xg), Q=f(p.Q), Ru=f(p.Ru), RK=f(p.RK),
+                           obs=f(p.obstacles.ravel()) if p.n_obs else None,
+                           u_lo=f(p.u_lo), u_hi=f(p.u_hi), x_lo=f(p.x_lo), x_hi=f(p.x_hi),
+                           u_init=f(p.u_init.ravel()), inertia=f(p.inertia), links=f(p.links))
+        s = Problem()
+        s.dyn, s.nx, s.nu, s.T = p.dyn, p.nx, p.nu, p.T
+        s.dt, s.radius, s.mass = p.dt, p.radius, p.mass
+        s.n_obs = p.n_obs
+        for k, a in self.arrays.items():
+            setattr(s, k, _ptr(a))
+        self.struct = s
+
+
+class Context:
+    """A batch of problems on one stream."""
+
+    def __init__(self, problems: Sequence, options: Optional[Options] = None, stream=None):
+        import torch
+        lib = load()
+        self.problems = list(problems)
+        self._holders = [_ProblemHolder(p) for p in self.problems]
+        arr = (Problem * len(self._holders))(*[h.struct for h in self._holders])
+        self._arr = arr
+        self.options = options if options is not None else default_options()
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        h = C.c_void_p()
+        _check(lib.nrto_setup(arr, len(self._holders), C.byref(self.options), C.c_void_p(stream), C.byref(h)))
+        self.h = h
+        self.n = len(self._holders)
+
+    def close(self):
+        if self.h:
+            load().nrto_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_options(self, options: Options):
+        self.options = options
+        _check(load().nrto_set_options(self.h, C.byref(options)), self.h)
+
+    def sizes(self, i: int) -> dict:
+        out = (C.c_int64 * 7)()
+        _check(load().nrto_instance_sizes(self.h, i, out), self.h)
+        keys = ["ng", "nent", "nblk", "nstate", "T", "nx", "nu"]
+        return {k: int(v) for k, v in zip(keys, out)}
+
+    def linearize(self):
+        _check(load().nrto_linearize(self.h), self.h)
+
+    def upload_socp(self, i, A, B, xhat, uhat, g0, w, bhat, bvec):
+        f = lambda a: np.ascontiguousarray(a, dtype=np.float64).ravel()
+        arrs = [f(a) for a in (A, B, xhat, uhat, g0, w, bhat, bvec)]
+        _check(load().nrto_upload_socp(self.h, i, *[_ptr(a) for a in arrs]), self.h)
+
+    def download_socp(self, i) -> dict:
+        s = self.sizes(i)
+        T, nx, nu, ng = s["T"], s["nx"], s["nu"], s["ng"]
+        out = dict(A=np.zeros(T * nx * nx), B=np.zeros(T * nx * nu), xhat=np.zeros((T + 1) * nx),
+                   uhat=np.zeros(T * nu), g0=np.zeros(ng), w=np.zeros(ng * nx),
+                   bhat=np.zeros(s["nent"]), bvec=np.zeros(s["nblk"] * nu))
+        _check(load().nrto_download_socp(self.h, i, *[_ptr(out[k]) for k in
+                                                       ("A", "B", "xhat", "uhat", "g0", "w", "bhat", "bvec")]), self.h)
+        return out
+
+    def solve(self, warm: bool = False) -> List[SolveReport]:
+        rep = (SolveReport * self.n)()
+        _check(load().nrto_solve_socp(self.h, 1 if warm else 0, rep), self.h)
+        return list(rep)
+
+    def solve_async(self, warm: bool = False):
+        _check(load().nrto_solve_socp(self.h, 1 if warm else 0, None), self.h)
+
+    def solution(self, i) -> dict:
+        s = self.sizes(i)
+        T, nx, nu, ng = s["T"], s["nx"], s["nu"], s["ng"]
+        out = dict(du=np.zeros(T * nu), K=np.zeros(T * nu * nx), p=np.zeros(ng), pt=np.zeros(ng),
+                   pi=np.zeros(ng), lam=np.zeros(ng), mu=np.zeros(1))
+        _check(load().nrto_get_solution(self.h, i, *[_ptr(out[k]) for k in
+                                                     ("du", "K", "p", "pt", "pi", "lam", "mu")]), self.h)
+        out["K"] = out["K"].reshape(T, nu, nx)
+        out["mu"] = float(out["mu"][0])
+        return out
+
+    def state(self, i) -> dict:
+        s = self.sizes(i)
+        T, nx, nu, ng = s["T"], s["nx"], s["nu"], s["ng"]
+        out = dict(st=np.zeros(s["nent"]), nu=np.zeros(s["nent"]), kt=np.zeros(T * nu * nx), ptt=np.zeros(ng))
+        _check(load().nrto_get_state(self.h, i, *[_ptr(out[k]) for k in ("st", "nu", "kt", "ptt")]), self.h)
+        out["kt"] = out["kt"].reshape(T, nu, nx)
+        return out
+
+    def set_state(self, i, st=None, nu=None, kt=None, ptt=None, du=None, K=None, p=None, pt=None, lam=None):
+        f = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float64).ravel()
+        arrs = [f(a) for a in (st, nu, kt, ptt, du, K, p, pt, lam)]
+        _check(load().nrto_set_state(self.h, i, *[_ptr(a) for a in arrs]), self.h)
+
+    def scp_step(self) -> List[StepReport]:
+        rep = (StepReport * self.n)()
+        _check(load().nrto_scp_step(self.h, rep), self.h)
+        return list(rep)
+
+    def nominal(self, i):
+        s = self.sizes(i)
+        T, nx, nu = s["T"], s["nx"], s["nu"]
+        u = np.zeros(T * nu)
+        K = np.zeros(T * nu * nx)
+        _check(load().nrto_get_nominal(self.h, i, _ptr(u), _ptr(K)), self.h)
+        return u.reshape(T, nu), K.reshape(T, nu, nx)

@@ -1,0 +1,97 @@
+"""GPU parity of the persistent solver against the oracle on the same SOCP
+data (produced by the oracle, marshalled into the compact layout):
+iterates after fixed iteration counts (no early stop) within 1e-9 relative in
+FP64, and the converged solves reaching the 1e-4 KKT residual."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dr, fulladmm, kkt, linearize
+
+from helpers import compact_socp, expand_entries, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def near_obstacle_problem(T=8, radius=0.05):
+    prob = synth.config1()
+    prob.T = T
+    prob.radius = radius
+    prob.u_init = np.tile([1.0, 0.0], (T, 1))
+    prob.obstacles = np.array([[0.45, 0.3, 0.15]])
+    return prob
+
+
+def _ctx(prob, s, **opt):
+    from paper_2603_02642_amd import nrto
+    o = nrto.default_options(**opt)
+    c = nrto.Context([prob], o)
+    c.upload_socp(0, **compact_socp(s))
+    return c
+
+
+@pytest.mark.parametrize("T,L,M,alpha", [(8, 3, 15, 1.0), (8, 2, 10, 1.6), (6, 2, 10, 0.5)])
+def test_dr_iterates_match_oracle_fp64(T, L, M, alpha):
+    _torch()
+    prob = near_obstacle_problem(T)
+    s = linearize.assemble(prob, prob.u_init, 5.0)
+    o = dr.Options(max_admm=L, max_dr=M, eps_kkt=0.0, eps_dr_abs=0.0, eps_dr_rel=0.0, alpha=alpha)
+    st, _ = dr.solve(s, o)
+    c = _ctx(prob, s, method=0, max_admm=L, max_inner=M, eps_kkt=0.0, eps_dr_abs=0.0, eps_dr_rel=0.0,
+             alpha=alpha, r_trust=5.0)
+    rep = c.solve()
+    g = c.solution(0)
+    gs = c.state(0)
+    assert rep[0].admm_iters == L and rep[0].inner_iters == L * M
+    assert rel_err(g["du"], st.du) <= 1e-9
+    assert rel_err(g["K"], st.K) <= 1e-9
+    assert rel_err(g["p"], st.p) <= 1e-9
+    assert rel_err(g["pt"], st.pt) <= 1e-9
+    assert rel_err(g["lam"], st.lam) <= 1e-9
+    assert rel_err(expand_entries(s, gs["st"]), st.s_t) <= 1e-9
+    assert rel_err(gs["kt"], st.K_t) <= 1e-9
+    ref_kkt = dr.residual(s, o, st)
+    assert abs(rep[0].kkt - ref_kkt) <= 1e-9 * max(1.0, ref_kkt)
+
+
+@pytest.mark.parametrize("T,L", [(8, 30), (5, 12)])
+def test_fulladmm_iterates_match_oracle_fp64(T, L):
+    _torch()
+    prob = near_obstacle_problem(T)
+    s = linearize.assemble(prob, prob.u_init, 5.0)
+    o = fulladmm.Options(max_admm=L, eps_kkt=0.0)
+    st, _ = fulladmm.solve(s, o)
+    c = _ctx(prob, s, method=1, max_admm=L, eps_kkt=0.0, rho=10.0, r_trust=5.0)
+    rep = c.solve()
+    g = c.solution(0)
+    gs = c.state(0)
+    assert rel_err(g["du"], st.du) <= 1e-9
+    assert rel_err(g["K"], st.K) <= 1e-9
+    assert rel_err(g["p"], st.p) <= 1e-9
+    assert rel_err(g["pt"], st.pt) <= 1e-9
+    assert rel_err(g["lam"], st.lam_p) <= 1e-9
+    assert rel_err(expand_entries(s, gs["st"])[:, 1:], st.lam_nu) <= 1e-9
+    assert rel_err(expand_entries(s, gs["nu"])[:, 1:], st.nu_) <= 1e-9
+    ref_kkt = fulladmm.residual(s, o, st)
+    assert abs(rep[0].kkt - ref_kkt) <= 1e-9 * max(1.0, ref_kkt)
+
+
+def test_trust_region_active_matches_oracle():
+    _torch()
+    prob = synth.config1()
+    s = linearize.assemble(prob, prob.u_init, 2.0)
+    o = fulladmm.Options(max_admm=6, eps_kkt=0.0)
+    st, _ = fulladmm.solve(s, o)
+    assert st.mu > 0
+    c = _ctx(prob, s, method=1, max_admm=6, eps_kkt=0.0, rho=10.0, r_trust=2.0)
+    c.solve()
+    g = c.solution(0)
+    assert abs(g["mu"] - st.mu) <= 1e-9 * max(1.0, st.mu)
+    assert rel_err(g["du"], st.du) <= 1e-9
