@@ -213,6 +213,21 @@ nrto_status nrto_set_state(nrto_ctx ctx, int32_t inst, const double *st, const d
                            const double *lam);
 
 /*
+ * Learned warm start of NRTO-DR (step a10): set the method state of every
+ * instance from a prediction row (device float32; row i at pred + i*ld) laid
+ * out as du (T*nu), K (T*nu*nx, K[k][u][x]), p~ (n_g), pi (n_g), through the DR
+ * fixed-point relations p = p~, lambda = -pi, s~ = (b - A chi) + y / sigma_s with
+ * y_j = pi_j (1, -eta_j / ||eta_j||), K~ = K.  With fallback_test != 0 the FP64
+ * KKT residual of the warm point is compared with that of the cold (zero)
+ * point and the cold point is kept when the warm one is worse.  accepted
+ * (host, n_inst, may be NULL) receives 1 where the warm point was kept;
+ * residuals (host, 2*n_inst, may be NULL) the (warm, cold) residuals.  Follow
+ * with nrto_solve_socp(ctx, 1, ...).  Requires method NRTO_DR.
+ */
+nrto_status nrto_warm_start(nrto_ctx ctx, const float *pred, int64_t ld, int32_t fallback_test,
+                            int32_t *accepted, double *residuals);
+
+/*
  * One successive-linearisation step for every instance: nrto_linearize, solve,
  * nonlinear rollout of the candidate, merit test, trust-region update and, on
  * acceptance, u_hat += du and the new gains.  rep: n_inst entries or NULL.
@@ -220,6 +235,41 @@ nrto_status nrto_set_state(nrto_ctx ctx, int32_t inst, const double *st, const d
 nrto_status nrto_scp_step(nrto_ctx ctx, nrto_step_report *rep);
 /* Current nominal controls of instance inst (T*nu) and gains (T*nu*nx, may be NULL). */
 nrto_status nrto_get_nominal(nrto_ctx ctx, int32_t inst, double *uhat, double *K);
+
+/*
+ * Learned warm start (a GELU MLP trained on solves of the method itself;
+ * the paper names learned warm starts as future work).  BF16 GEMM operands on
+ * the matrix cores, FP32 accumulation, FP32 master weights, Adam.
+ *  widths     layer widths w_0 .. w_L (host, n_widths = L + 1 >= 2)
+ *  max_batch  largest batch passed to infer / train_step / gradients
+ *  seed       SplitMix64 seed of the initial weights U(+-sqrt(6/(fan_in+fan_out)))
+ *  stream     hipStream_t for every call on this handle
+ * X, T, Y are device float32 arrays, row-major (batch x w_0, batch x w_L).
+ * Inputs are standardised with (xmean, xstd) and targets with (ymean, ystd)
+ * (nrto_ws_set_norm, host arrays; default 0 / 1); nrto_ws_infer returns
+ * de-standardised outputs.  Loss: mean squared error on standardised targets.
+ */
+typedef struct nrto_ws_s *nrto_ws;
+nrto_status nrto_ws_create(const int32_t *widths, int32_t n_widths, int32_t max_batch, uint64_t seed,
+                           void *stream, nrto_ws *out);
+void nrto_ws_destroy(nrto_ws ws);
+nrto_status nrto_ws_set_norm(nrto_ws ws, const float *xmean, const float *xstd, const float *ymean,
+                             const float *ystd);
+nrto_status nrto_ws_infer(nrto_ws ws, const float *X, int32_t batch, float *Y);
+/* One Adam step (lr, betas 0.9 / 0.999, eps 1e-8); loss_host may be NULL (no sync). */
+nrto_status nrto_ws_train_step(nrto_ws ws, const float *X, const float *T, int32_t batch, float lr,
+                               float *loss_host);
+/* Gradients without an update, to host memory in the order W_0, b_0, W_1, b_1, ...
+ * (W_l is w_{l+1} x w_l row-major). */
+nrto_status nrto_ws_gradients(nrto_ws ws, const float *X, const float *T, int32_t batch, float *grads,
+                              float *loss_host);
+/* Read (get != NULL) and/or write (set != NULL) the FP32 master parameters, same order. */
+nrto_status nrto_ws_params(nrto_ws ws, float *get, const float *set);
+/* The BF16 matrix-core GEMM the network uses: C (M x N, float32, row-major) =
+ * A B with A[m][k] = A[m*sam + k*sak], B[k][n] = B[k*sbk + n*sbn] (bf16 bit
+ * patterns, device memory). */
+nrto_status nrto_ws_gemm_bf16(const uint16_t *A, int64_t sam, int64_t sak, const uint16_t *B, int64_t sbk,
+                              int64_t sbn, int32_t M, int32_t N, int32_t K, float *C, void *stream);
 
 #ifdef __cplusplus
 }

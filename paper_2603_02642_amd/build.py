@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnrto.so")
-SOURCES = ["project_soc.hip", "solver.hip", "linearize.hip", "context.hip"]
+SOURCES = ["project_soc.hip", "solver.hip", "linearize.hip", "context.hip", "mlp.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]

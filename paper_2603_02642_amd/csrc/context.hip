@@ -16,7 +16,10 @@ size_t solver_smem_bytes(int T, int nx, int nu, int precision, int threads);
 hipError_t launch_solver(const DevPtrs& g, const SolveOpts& o, int nx, const int32_t* order, int n, int threads,
                          size_t smem, hipStream_t s);
 hipError_t set_solver_smem_limit(size_t bytes);
+hipError_t launch_warm(const DevPtrs& g, const SolveOpts& o, int nx, const int32_t* order, int n, int threads,
+                       size_t smem, const float* pred, int64_t ld, int test, int32_t* acc, double* res, hipStream_t s);
 hipError_t launch_linearize(const DevPtrs& g, int n_inst, int max_ng, hipStream_t s);
+hipError_t launch_scp_eval(const DevPtrs& g, int n_inst, double w_p, double* out, hipStream_t s);
 
 static thread_local std::string g_err;
 
@@ -656,6 +659,63 @@ extern "C" nrto_status nrto_get_nominal(nrto_ctx c, int32_t inst, double* uhat, 
 
 extern "C" nrto_status nrto_scp_step(nrto_ctx c, nrto_step_report* rep) {
   if (!c) return set_global_error(NRTO_ERR_ARG, "null context");
-  (void)rep;
-  return ctx_err(c, NRTO_ERR_STATE, "nrto_scp_step is not available in this build");
+  nrto_status s = nrto_linearize(c);
+  if (s != NRTO_OK) return s;
+  std::vector<nrto_solve_report> sr(c->n);
+  // the KKT residual (and the robust margins the merit test reads) must be evaluated
+  nrto_options keep = c->opt;
+  if (!(c->opt.eps_kkt > 0.0)) c->opt.eps_kkt = 1e-300;
+  s = nrto_solve_socp(c, 0, sr.data());
+  c->opt = keep;
+  if (s != NRTO_OK) return s;
+  double* out = nullptr;
+  if (hipMalloc(&out, sizeof(double) * 5 * c->n) != hipSuccess) return ctx_err(c, NRTO_ERR_ALLOC, "hipMalloc failed");
+  std::vector<double> h(5 * (size_t)c->n);
+  hipError_t e = launch_scp_eval(c->g, c->n, 10.0, out, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), out, sizeof(double) * 5 * c->n, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  hipFree(out);
+  if (e != hipSuccess) return ctx_err(c, NRTO_ERR_HIP, hipGetErrorString(e));
+  if (rep)
+    for (int i = 0; i < c->n; ++i) {
+      rep[i].accepted = (int)h[5 * i];
+      rep[i].status = sr[i].status;
+      rep[i].merit_old = h[5 * i + 1];
+      rep[i].merit_new = h[5 * i + 2];
+      rep[i].predicted = h[5 * i + 3];
+      rep[i].r_trust = h[5 * i + 4];
+      rep[i].kkt = sr[i].kkt;
+    }
+  return NRTO_OK;
+}
+
+extern "C" nrto_status nrto_warm_start(nrto_ctx c, const float* pred, int64_t ld, int32_t fallback_test,
+                                       int32_t* accepted, double* residuals) {
+  if (!c || !pred) return set_global_error(NRTO_ERR_ARG, "null argument");
+  if (c->opt.method != NRTO_DR) return ctx_err(c, NRTO_ERR_STATE, "the learned warm start targets NRTO-DR");
+  for (auto& h : c->hi)
+    if (ld < (int64_t)h.d.T * h.d.nu * (h.d.nx + 1) + 2 * (int64_t)h.d.ng)
+      return ctx_err(c, NRTO_ERR_ARG, "prediction row shorter than du + K + p~ + pi");
+  int32_t* acc = nullptr;
+  double* res = nullptr;
+  if (hipMalloc(&acc, sizeof(int32_t) * c->n) != hipSuccess) return ctx_err(c, NRTO_ERR_ALLOC, "hipMalloc failed");
+  if (hipMalloc(&res, sizeof(double) * 2 * c->n) != hipSuccess) {
+    (void)hipFree(acc);
+    return ctx_err(c, NRTO_ERR_ALLOC, "hipMalloc failed");
+  }
+  SolveOpts o;
+  fill_opts(c, o, 1);
+  hipError_t e = hipSuccess;
+  for (int gi = 0; gi < 3 && e == hipSuccess; ++gi) {
+    const int cnt = c->group_off[gi + 1] - c->group_off[gi];
+    e = launch_warm(c->g, o, c->group_nx[gi], c->order + c->group_off[gi], cnt, c->threads, c->smem, pred, ld,
+                    fallback_test ? 1 : 0, acc, res, c->stream);
+  }
+  if (e == hipSuccess && accepted) e = hipMemcpyAsync(accepted, acc, sizeof(int32_t) * c->n, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess && residuals) e = hipMemcpyAsync(residuals, res, sizeof(double) * 2 * c->n, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(acc);
+  (void)hipFree(res);
+  if (e != hipSuccess) return ctx_err(c, NRTO_ERR_HIP, hipGetErrorString(e));
+  return NRTO_OK;
 }

@@ -191,44 +191,15 @@ __global__ void rollout_kernel(DevPtrs g) {
   else rollout_and_jac<14, 7>(g, ii);
 }
 
+// Value and state gradient of state constraint j (time slice entry) at x_t.
 template <int NX, int NU>
-__device__ void cone_data(const DevPtrs& g, const InstDev& d, int j) {
-  const int32_t* m = g.cmeta + (d.cone0 + j) * CM_N;
+__device__ double state_cons_eval(const DevPtrs& g, const InstDev& d, int j, const int32_t* m, const double* xt,
+                                  double* w) {
   const double* prm = g.prm + d.oP;
   const ParamOffsets po = param_offsets(NX, NU, d.n_obs);
-  const double* xh = g.xhat + d.oX;
-  const double* uh = g.uhat + d.oU;
-  const int e0 = m[CM_EOFF], nb = m[CM_NBLK], bo = m[CM_BOFF];
-  double* bh = g.bhat64 + d.ent0 + e0;
-  float* bh32 = g.bhat32 + d.ent0 + e0;
-  double* bv = g.bvec64 + d.bv0 + (int64_t)bo * NU;
-  float* bv32 = g.bvec32 + d.bv0 + (int64_t)bo * NU;
-  double* wout = g.w + d.oW + (int64_t)j * NX;
-  double* g0 = g.carr + (int64_t)CA_G0 * g.ncones + d.cone0 + j;
-  const double r = d.radius;
-  bh[0] = 0.0;
-  bh32[0] = 0.0f;
-  if (m[CM_KIND] == 1) {
-    const int k = m[CM_TIME], i = m[CM_CIDX], s = m[CM_CSIGN];
-    const double bound = (s > 0) ? prm[po.uhi + i] : prm[po.ulo + i];
-    *g0 = s * uh[k * NU + i] - s * bound;
-    for (int l = 0; l < NX; ++l) {
-      bh[1 + l] = 0.0;
-      bh32[1 + l] = 0.0f;
-      wout[l] = 0.0;
-    }
-    for (int u = 0; u < NU; ++u) {
-      bv[u] = (u == i) ? (double)s : 0.0;
-      bv32[u] = (float)bv[u];
-    }
-    return;
-  }
-  const int t = m[CM_TIME];
-  const double* xt = xh + t * NX;
-  double w[NX];
   for (int l = 0; l < NX; ++l) w[l] = 0.0;
   const int npts = (d.dyn == NRTO_DYN_ARM) ? 7 : 1;
-  // index of this constraint inside its time slice
+  const int t = m[CM_TIME];
   const int32_t* tls = g.tl + d.oTL;
   const int jj = j - tls[t];
   double gv;
@@ -274,6 +245,46 @@ __device__ void cone_data(const DevPtrs& g, const InstDev& d, int j) {
       w[i] = -1.0;
     }
   }
+  return gv;
+}
+
+template <int NX, int NU>
+__device__ void cone_data(const DevPtrs& g, const InstDev& d, int j) {
+  const int32_t* m = g.cmeta + (d.cone0 + j) * CM_N;
+  const double* prm = g.prm + d.oP;
+  const ParamOffsets po = param_offsets(NX, NU, d.n_obs);
+  const double* xh = g.xhat + d.oX;
+  const double* uh = g.uhat + d.oU;
+  const int e0 = m[CM_EOFF], nb = m[CM_NBLK], bo = m[CM_BOFF];
+  double* bh = g.bhat64 + d.ent0 + e0;
+  float* bh32 = g.bhat32 + d.ent0 + e0;
+  double* bv = g.bvec64 + d.bv0 + (int64_t)bo * NU;
+  float* bv32 = g.bvec32 + d.bv0 + (int64_t)bo * NU;
+  double* wout = g.w + d.oW + (int64_t)j * NX;
+  double* g0 = g.carr + (int64_t)CA_G0 * g.ncones + d.cone0 + j;
+  const double r = d.radius;
+  bh[0] = 0.0;
+  bh32[0] = 0.0f;
+  if (m[CM_KIND] == 1) {
+    const int k = m[CM_TIME], i = m[CM_CIDX], s = m[CM_CSIGN];
+    const double bound = (s > 0) ? prm[po.uhi + i] : prm[po.ulo + i];
+    *g0 = s * uh[k * NU + i] - s * bound;
+    for (int l = 0; l < NX; ++l) {
+      bh[1 + l] = 0.0;
+      bh32[1 + l] = 0.0f;
+      wout[l] = 0.0;
+    }
+    for (int u = 0; u < NU; ++u) {
+      bv[u] = (u == i) ? (double)s : 0.0;
+      bv32[u] = (float)bv[u];
+    }
+    return;
+  }
+  const int t = m[CM_TIME];
+  const double* xt = xh + t * NX;
+  double w[NX];
+  const double gv = state_cons_eval<NX, NU>(g, d, j, m, xt, w);
+  (void)po;
   *g0 = gv;
   for (int l = 0; l < NX; ++l) wout[l] = w[l];
   // adjoint recursion; block t first (b = 0)
@@ -319,6 +330,132 @@ __global__ void cone_data_kernel(DevPtrs g, int n_inst) {
     else if (d.nx == 12) cone_data<12, 4>(g, d, j);
     else cone_data<14, 7>(g, d, j);
   }
+}
+
+// Trust-region test of one successive-linearisation step (see the oracle's scp
+// module for the merit definitions).  One workgroup per instance; out[4*ii..]
+// receives (accepted, merit_cur, merit_act, merit_pred).
+template <int NX, int NU>
+__device__ void scp_eval(const DevPtrs& g, int ii, double w_p, double* out) {
+  InstDev& d = g.inst[ii];
+  const int T = d.T;
+  const double* prm = g.prm + d.oP;
+  const ParamOffsets po = param_offsets(NX, NU, d.n_obs);
+  const double* xh = g.xhat + d.oX;
+  double* uh = g.uhat + d.oU;
+  const double* du = g.du + d.oU;
+  const double* dx = g.dx + d.oX;
+  double* x1 = g.dx2 + d.oX;    // QP scratch is free after the solve
+  double* u1 = g.du2 + d.oU;
+  const double* Q = prm + po.Q;
+  const double* Ru = prm + po.Ru;
+  const double* xg = prm + po.xg;
+  __shared__ double red[3 * 16];
+  if (threadIdx.x == 0) {
+    double x[NX], f[NX];
+    for (int i = 0; i < NX; ++i) x[i] = prm[po.x0 + i];
+    for (int i = 0; i < NX; ++i) x1[i] = x[i];
+    for (int k = 0; k < T; ++k) {
+      for (int u = 0; u < NU; ++u) u1[k * NU + u] = uh[k * NU + u] + du[k * NU + u];
+      xdot_dev<NX, NU>(d.dyn, prm, po, d.mass, x, u1 + k * NU, f);
+      for (int i = 0; i < NX; ++i) x[i] += d.dt * f[i];
+      for (int i = 0; i < NX; ++i) x1[(k + 1) * NX + i] = x[i];
+    }
+  }
+  __syncthreads();
+  // costs: J(u_hat), Q_u(du), J(u_hat + du)
+  double c0 = 0.0, cp = 0.0, c1 = 0.0;
+  for (int k = threadIdx.x; k < T; k += blockDim.x) {
+    for (int a = 0; a < NU; ++a)
+      for (int b = 0; b < NU; ++b) {
+        const double r = Ru[a * NU + b];
+        c0 += uh[k * NU + a] * r * uh[k * NU + b];
+        cp += (uh[k * NU + a] + du[k * NU + a]) * r * (uh[k * NU + b] + du[k * NU + b]);
+        c1 += u1[k * NU + a] * r * u1[k * NU + b];
+      }
+    const int t = k + 1;
+    for (int a = 0; a < NX; ++a)
+      for (int b = 0; b < NX; ++b) {
+        const double q = Q[a * NX + b];
+        c0 += (xh[t * NX + a] - xg[a]) * q * (xh[t * NX + b] - xg[b]);
+        cp += (xh[t * NX + a] + dx[t * NX + a] - xg[a]) * q * (xh[t * NX + b] + dx[t * NX + b] - xg[b]);
+        c1 += (x1[t * NX + a] - xg[a]) * q * (x1[t * NX + b] - xg[b]);
+      }
+  }
+  // penalties
+  const double* carr = g.carr;
+  const int64_t nc = g.ncones;
+  for (int j = threadIdx.x; j < d.ng; j += blockDim.x) {
+    const int32_t* m = g.cmeta + (d.cone0 + j) * CM_N;
+    const double g0 = carr[(int64_t)CA_G0 * nc + d.cone0 + j];
+    const double n = carr[(int64_t)CA_N * nc + d.cone0 + j];
+    double lin, gnew;
+    if (m[CM_KIND] == 1) {
+      const int k = m[CM_TIME], i = m[CM_CIDX], s = m[CM_CSIGN];
+      const double bound = (s > 0) ? prm[po.uhi + i] : prm[po.ulo + i];
+      lin = s * du[k * NU + i];
+      gnew = s * u1[k * NU + i] - s * bound;
+    } else {
+      const double* w = g.w + d.oW + (int64_t)j * NX;
+      const int t = m[CM_TIME];
+      lin = 0.0;
+      for (int a = 0; a < NX; ++a) lin += w[a] * dx[t * NX + a];
+      double wtmp[NX];
+      gnew = state_cons_eval<NX, NU>(g, d, j, m, x1 + t * NX, wtmp);
+    }
+    c0 += w_p * fmax(0.0, g0 + n);
+    cp += w_p * fmax(0.0, g0 + lin + n);
+    c1 += w_p * fmax(0.0, gnew + n);
+  }
+  c0 = wave_sum(c0);
+  cp = wave_sum(cp);
+  c1 = wave_sum(c1);
+  if (lane_id() == 0) {
+    red[wave_id() * 3 + 0] = c0;
+    red[wave_id() * 3 + 1] = cp;
+    red[wave_id() * 3 + 2] = c1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double cur = 0.0, pred = 0.0, act = 0.0;
+    for (int w = 0; w < (int)(blockDim.x / NRTO_WAVE); ++w) {
+      cur += red[w * 3];
+      pred += red[w * 3 + 1];
+      act += red[w * 3 + 2];
+    }
+    const double dpred = cur - pred;
+    const double ratio = dpred > 0.0 ? (cur - act) / dpred : -1e300;
+    const bool acc = dpred > 0.0 && ratio >= 0.1;
+    double r = d.r_trust;
+    if (acc) {
+      if (ratio >= 0.75) r = fmin(1.5 * r, 1e3);
+    } else {
+      r = fmax(0.8 * r, 1e-3);
+    }
+    d.r_trust = r;
+    out[ii * 5 + 0] = acc ? 1.0 : 0.0;
+    out[ii * 5 + 1] = cur;
+    out[ii * 5 + 2] = act;
+    out[ii * 5 + 3] = pred;
+    out[ii * 5 + 4] = r;
+    red[47] = acc ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  if (red[47] != 0.0)
+    for (int i = threadIdx.x; i < T * NU; i += blockDim.x) uh[i] = u1[i];
+}
+
+__global__ void scp_eval_kernel(DevPtrs g, double w_p, double* out) {
+  const int ii = blockIdx.x;
+  const int nx = g.inst[ii].nx;
+  if (nx == 3) scp_eval<3, 2>(g, ii, w_p, out);
+  else if (nx == 12) scp_eval<12, 4>(g, ii, w_p, out);
+  else scp_eval<14, 7>(g, ii, w_p, out);
+}
+
+hipError_t launch_scp_eval(const DevPtrs& g, int n_inst, double w_p, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(scp_eval_kernel, dim3(n_inst), dim3(256), 0, s, g, w_p, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_linearize(const DevPtrs& g, int n_inst, int max_ng, hipStream_t s) {

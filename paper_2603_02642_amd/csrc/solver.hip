@@ -1459,6 +1459,154 @@ __device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, cha
   }
 }
 
+// ----------------------------------------------------------------------------
+// Learned warm start for NRTO-DR: set the method state from a prediction
+// (du, K, p~, pi) through the DR fixed-point relations: p = p~, lambda = -pi,
+// chi = (k_v, p~), s = b - A chi, y_j = pi_j (1, -eta_j / ||eta_j||) (zero when
+// eta_j = 0), s~ = s + y / sigma_s, K~ = K, p~~ = p~.  The KKT residual of the
+// warm point is compared with that of the cold (zero) point; the cold point is
+// kept when the warm one is worse.
+template <int NX, int NU, typename F>
+__device__ void warm_pass(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o) {
+  const int T = I.T;
+  const F r = (F)I.r;
+  const double inv_s = 1.0 / o.sigma_s;
+  for (int t = next_task(S.ctr); t < I.ntask; t = next_task(S.ctr)) {
+    const WaveTask tk = I.tasks[t];
+    for (int c = tk.cone; c < tk.cone + tk.ncone; ++c) {
+      const int32_t* m = I.cm + c * CM_N;
+      const int e0 = m[CM_EOFF];
+      const int len = 1 + m[CM_NBLK] * NX;
+      double n2 = 0.0;
+      for (int le = 1 + lane_id(); le < len; le += NRTO_WAVE) {
+        int k, x, b;
+        entry_block<NX>(m, le, k, x, b);
+        const double eta = (double)(r * fwd_gemm<NX, NU, F>(I, S, T, k, x, I.bvec + (int64_t)b * NU) + I.bhat[e0 + le]);
+        n2 += eta * eta;
+      }
+      const double nrm = sqrt(wave_sum(n2));
+      const double pi = I.C(CA_PI, c);
+      const double pt = I.C(CA_PT, c);
+      for (int le = lane_id(); le < len; le += NRTO_WAVE) {
+        if (le == 0) {
+          I.st[e0] = (F)(pt + pi * inv_s);
+        } else {
+          int k, x, b;
+          entry_block<NX>(m, le, k, x, b);
+          const double eta = (double)(r * fwd_gemm<NX, NU, F>(I, S, T, k, x, I.bvec + (int64_t)b * NU) + I.bhat[e0 + le]);
+          const double y = (nrm > 0.0) ? -pi * eta / nrm : 0.0;
+          I.st[e0 + le] = (F)(eta + y * inv_s);
+        }
+      }
+    }
+  }
+}
+
+template <int NX, int NU, typename F>
+__device__ void zero_state(const Inst<NX, NU, F>& I) {
+  const int T = I.T;
+  for (int64_t e = threadIdx.x; e < I.nent; e += blockDim.x) {
+    I.st[e] = (F)0;
+    I.nuv[e] = (F)0;
+  }
+  for (int c = threadIdx.x; c < I.ng; c += blockDim.x) {
+    I.C(CA_P, c) = 0.0;
+    I.C(CA_PT, c) = 0.0;
+    I.C(CA_PTT, c) = 0.0;
+    I.C(CA_LAM, c) = 0.0;
+    I.C(CA_PI, c) = 0.0;
+    I.C(CA_ACT, c) = 0.0;
+  }
+  for (int i = threadIdx.x; i < T * NU * NX; i += blockDim.x) {
+    I.K[i] = 0.0;
+    I.Kt[i] = 0.0;
+  }
+  for (int i = threadIdx.x; i < T * NU; i += blockDim.x) I.du[i] = 0.0;
+  for (int i = threadIdx.x; i < (T + 1) * NX; i += blockDim.x) I.dx[i] = 0.0;
+  if (threadIdx.x == 0) {
+    *I.mu = 0.0;
+    I.flags[0] = 0;
+    I.iscr[ISCR_PSI] = 0.0;
+  }
+  __syncthreads();
+}
+
+template <int NX, int NU, typename F>
+__global__ void __launch_bounds__(NRTO_SOLVER_MAX_THREADS)
+warm_kernel(DevPtrs g, SolveOpts o, const int32_t* order, int n, const float* pred, int64_t ld, int test,
+            int32_t* accepted, double* res) {
+  extern __shared__ __align__(16) char smem[];
+  const int ii = order[blockIdx.x];
+  Inst<NX, NU, F> I = make_inst<NX, NU, F>(g, ii);
+  const int W = blockDim.x / NRTO_WAVE;
+  Smem<F> S = carve<F>(smem, I.T, NX, NU, W);
+  const int T = I.T;
+  double r_cold = 1e300;
+  zero_state<NX, NU, F>(I);
+  if (test) {
+    load_kf<NX, NU, F>(I, S);
+    r_cold = kkt_residual<NX, NU, F, NRTO_DR>(I, S, o, false, W);
+  }
+  // prediction row of this instance: du (T*NU), K (T*NU*NX as K[k][u][x]), p~ (ng), pi (ng)
+  const float* pr = pred + (int64_t)ii * ld;
+  for (int i = threadIdx.x; i < T * NU; i += blockDim.x) I.du[i] = (double)pr[i];
+  pr += T * NU;
+  for (int i = threadIdx.x; i < T * NU * NX; i += blockDim.x) {
+    I.K[i] = (double)pr[i];
+    I.Kt[i] = (double)pr[i];
+  }
+  pr += T * NU * NX;
+  for (int c = threadIdx.x; c < I.ng; c += blockDim.x) {
+    const double pt = (double)pr[c];
+    const double pi = fmax(0.0, (double)pr[I.ng + c]);
+    I.C(CA_PT, c) = pt;
+    I.C(CA_PTT, c) = pt;
+    I.C(CA_P, c) = pt;
+    I.C(CA_PI, c) = pi;
+    I.C(CA_LAM, c) = -pi;
+  }
+  __syncthreads();
+  load_kf<NX, NU, F>(I, S);
+  if (wave_id() == 0) {
+    rollout_dx<NX, NU, F>(I);
+    const double psi = state_norm<NX, NU, F>(I);
+    if (lane_id() == 0) I.iscr[ISCR_PSI] = psi;
+  }
+  if (threadIdx.x == 0) *S.ctr = 0;
+  __syncthreads();
+  warm_pass<NX, NU, F>(I, S, o);
+  __syncthreads();
+  double r_warm = 0.0;
+  if (test) r_warm = kkt_residual<NX, NU, F, NRTO_DR>(I, S, o, false, W);
+  const bool keep = !test || r_warm <= r_cold;
+  if (!keep) zero_state<NX, NU, F>(I);
+  if (threadIdx.x == 0) {
+    accepted[ii] = keep ? 1 : 0;
+    res[2 * ii] = r_warm;
+    res[2 * ii + 1] = r_cold;
+  }
+}
+
+template <int NX, int NU>
+static hipError_t launch_warm_nxnu(const DevPtrs& g, const SolveOpts& o, const int32_t* order, int n, int threads,
+                                   size_t smem, const float* pred, int64_t ld, int test, int32_t* acc, double* res,
+                                   hipStream_t s) {
+  dim3 grid(n), block(threads);
+  if (o.precision == NRTO_FP32)
+    hipLaunchKernelGGL((warm_kernel<NX, NU, float>), grid, block, smem, s, g, o, order, n, pred, ld, test, acc, res);
+  else
+    hipLaunchKernelGGL((warm_kernel<NX, NU, double>), grid, block, smem, s, g, o, order, n, pred, ld, test, acc, res);
+  return hipGetLastError();
+}
+
+hipError_t launch_warm(const DevPtrs& g, const SolveOpts& o, int nx, const int32_t* order, int n, int threads,
+                       size_t smem, const float* pred, int64_t ld, int test, int32_t* acc, double* res, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (nx == 3) return launch_warm_nxnu<3, 2>(g, o, order, n, threads, smem, pred, ld, test, acc, res, s);
+  if (nx == 12) return launch_warm_nxnu<12, 4>(g, o, order, n, threads, smem, pred, ld, test, acc, res, s);
+  return launch_warm_nxnu<14, 7>(g, o, order, n, threads, smem, pred, ld, test, acc, res, s);
+}
+
 template <int NX, int NU, typename F, int METHOD>
 __global__ void __launch_bounds__(NRTO_SOLVER_MAX_THREADS) solve_kernel(DevPtrs g, SolveOpts o, const int32_t* order, int n) {
   extern __shared__ __align__(16) char smem[];
@@ -1501,6 +1649,10 @@ hipError_t launch_solver(const DevPtrs& g, const SolveOpts& o, int nx, const int
 template <int NX, int NU>
 static hipError_t smem_attr(size_t bytes) {
   hipError_t e;
+  e = hipFuncSetAttribute((const void*)warm_kernel<NX, NU, float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)warm_kernel<NX, NU, double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void*)solve_kernel<NX, NU, float, NRTO_DR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void*)solve_kernel<NX, NU, float, NRTO_FULLADMM>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);

@@ -84,6 +84,7 @@ def load() -> C.CDLL:
         "nrto_set_state": (i32, [vp, i32] + [_dp] * 9),
         "nrto_scp_step": (i32, [vp, P(StepReport)]),
         "nrto_get_nominal": (i32, [vp, i32, _dp, _dp]),
+        "nrto_warm_start": (i32, [vp, vp, i64, i32, P(C.c_int32), _dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -244,6 +245,15 @@ class Context:
         arrs = [f(a) for a in (st, nu, kt, ptt, du, K, p, pt, lam)]
         _check(load().nrto_set_state(self.h, i, *[_ptr(a) for a in arrs]), self.h)
 
+    def warm_start(self, pred, ld=None, fallback_test=True):
+        """Set the NRTO-DR state from prediction rows (torch float32 tensor on the GPU)."""
+        acc = np.zeros(self.n, dtype=np.int32)
+        res = np.zeros(2 * self.n)
+        ld = pred.shape[1] if ld is None else ld
+        _check(load().nrto_warm_start(self.h, C.c_void_p(pred.data_ptr()), ld, 1 if fallback_test else 0,
+                                      acc.ctypes.data_as(C.POINTER(C.c_int32)), _ptr(res)), self.h)
+        return acc, res.reshape(self.n, 2)
+
     def scp_step(self) -> List[StepReport]:
         rep = (StepReport * self.n)()
         _check(load().nrto_scp_step(self.h, rep), self.h)
@@ -256,3 +266,115 @@ class Context:
         K = np.zeros(T * nu * nx)
         _check(load().nrto_get_nominal(self.h, i, _ptr(u), _ptr(K)), self.h)
         return u.reshape(T, nu), K.reshape(T, nu, nx)
+
+
+def _ws_sigs(lib):
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    fp = C.POINTER(C.c_float)
+    sig = {
+        "nrto_ws_create": (i32, [C.POINTER(C.c_int32), i32, i32, C.c_uint64, vp, C.POINTER(vp)]),
+        "nrto_ws_destroy": (None, [vp]),
+        "nrto_ws_set_norm": (i32, [vp, fp, fp, fp, fp]),
+        "nrto_ws_infer": (i32, [vp, vp, i32, vp]),
+        "nrto_ws_train_step": (i32, [vp, vp, vp, i32, C.c_float, fp]),
+        "nrto_ws_gradients": (i32, [vp, vp, vp, i32, fp, fp]),
+        "nrto_ws_params": (i32, [vp, fp, fp]),
+        "nrto_ws_gemm_bf16": (i32, [vp, i64, i64, vp, i64, i64, i32, i32, i32, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+
+
+def _fptr(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+class WarmStartNet:
+    """GELU MLP on the matrix cores (nrto_ws_*).  Tensors are torch float32 on the GPU."""
+
+    def __init__(self, widths, max_batch, seed=0, stream=None):
+        import torch
+        lib = load()
+        _ws_sigs(lib)
+        self.widths = [int(w) for w in widths]
+        self.max_batch = int(max_batch)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        arr = (C.c_int32 * len(self.widths))(*self.widths)
+        h = C.c_void_p()
+        _check(lib.nrto_ws_create(arr, len(self.widths), self.max_batch, seed, C.c_void_p(stream), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            load().nrto_ws_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_norm(self, xmean, xstd, ymean, ystd):
+        f = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float32)
+        a = [f(x) for x in (xmean, xstd, ymean, ystd)]
+        _check(load().nrto_ws_set_norm(self.h, *[_fptr(x) for x in a]))
+
+    def infer(self, X, out=None):
+        import torch
+        if out is None:
+            out = torch.empty((X.shape[0], self.widths[-1]), dtype=torch.float32, device=X.device)
+        _check(load().nrto_ws_infer(self.h, C.c_void_p(X.data_ptr()), X.shape[0], C.c_void_p(out.data_ptr())))
+        return out
+
+    def train_step(self, X, T, lr=1e-3, want_loss=True):
+        loss = np.zeros(1, dtype=np.float32)
+        _check(load().nrto_ws_train_step(self.h, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()), X.shape[0],
+                                         float(lr), _fptr(loss) if want_loss else None))
+        return float(loss[0])
+
+    def _nparams(self):
+        return sum(self.widths[l] * self.widths[l + 1] + self.widths[l + 1] for l in range(len(self.widths) - 1))
+
+    def _split(self, flat):
+        out, off = [], 0
+        for l in range(len(self.widths) - 1):
+            fi, fo = self.widths[l], self.widths[l + 1]
+            W = flat[off:off + fi * fo].reshape(fo, fi)
+            off += fi * fo
+            b = flat[off:off + fo]
+            off += fo
+            out.append([W.copy(), b.copy()])
+        return out
+
+    def gradients(self, X, T):
+        g = np.zeros(self._nparams(), dtype=np.float32)
+        loss = np.zeros(1, dtype=np.float32)
+        _check(load().nrto_ws_gradients(self.h, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()), X.shape[0],
+                                        _fptr(g), _fptr(loss)))
+        return self._split(g), float(loss[0])
+
+    def get_params(self):
+        p = np.zeros(self._nparams(), dtype=np.float32)
+        _check(load().nrto_ws_params(self.h, _fptr(p), None))
+        return self._split(p)
+
+    def set_params(self, params):
+        flat = np.concatenate([np.concatenate([np.asarray(W, np.float32).ravel(), np.asarray(b, np.float32).ravel()])
+                               for W, b in params]).astype(np.float32)
+        _check(load().nrto_ws_params(self.h, None, _fptr(flat)))
+
+
+def gemm_bf16(A_bits, sam, sak, B_bits, sbk, sbn, M, N, K, C_out, stream=None):
+    """C_out (M x N float32) = A B on the matrix cores; A_bits, B_bits are int16 tensors of bf16 patterns."""
+    import torch
+    lib = load()
+    _ws_sigs(lib)
+    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    _check(lib.nrto_ws_gemm_bf16(C.c_void_p(A_bits.data_ptr()), sam, sak, C.c_void_p(B_bits.data_ptr()), sbk, sbn,
+                                 M, N, K, C.c_void_p(C_out.data_ptr()), C.c_void_p(s)))
+    return C_out
