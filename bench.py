@@ -24,10 +24,12 @@ sys.path.insert(0, ROOT)
 import synth  # noqa: E402
 
 WORKLOADS = {
-    # name: (description, builder, options)
     "quadrotor_T50_plain": "quadrotor n_x=12 n_u=4 T=50, 5 obstacles, ball radius 0.05, one instance, cold start",
-    "mixed_batch_2048": "2048 mixed instances (1024 unicycle + 1024 quadrotor), T~U{20..80}, 1-10 obstacles",
+    "mixed_batch_2048": "2048 mixed instances (1024 unicycle + 1024 quadrotor), T~U{20..80}, 1-10 obstacles, cold start",
+    "learned_quadrotor_4096": "4096 held-out quadrotor instances (T=50, 10 obstacles), learned warm start + cold fallback",
+    "plain_quadrotor_4096": "the same 4096 held-out quadrotor instances, cold start",
 }
+WEIGHTS = os.path.join(ROOT, "paper_2603_02642_amd", "weights", "ws_quadrotor_T50.npz")
 
 HBM_PEAK_GBS = 8000.0
 
@@ -38,6 +40,8 @@ def _problems(name, n=None):
     if name == "mixed_batch_2048":
         m = n or 2048
         return [synth.config4_instance(i if i < m // 2 else 1024 + (i - m // 2)) for i in range(m)]
+    if name in ("learned_quadrotor_4096", "plain_quadrotor_4096"):
+        return [synth.config5_instance(i, "heldout") for i in range(n or 4096)]
     raise KeyError(name)
 
 
@@ -73,12 +77,14 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="quadrotor_T50_plain", choices=list(WORKLOADS))
-    ap.add_argument("--method", type=int, default=1, help="0 NRTO-DR, 1 FullADMM")
+    ap.add_argument("--method", type=int, default=0, help="0 NRTO-DR, 1 FullADMM")
     ap.add_argument("--precision", type=int, default=0, help="0 FP64, 1 FP32")
-    ap.add_argument("--max-admm", type=int, default=400)
+    ap.add_argument("--max-admm", type=int, default=200)
     ap.add_argument("--max-inner", type=int, default=100)
-    ap.add_argument("--check-every", type=int, default=5)
+    ap.add_argument("--check-every", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="only run a device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only"}))
@@ -87,6 +93,16 @@ def main():
     import torch
     from paper_2603_02642_amd import nrto
 
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_each_way": n * 4, "launches": 3}), flush=True)
+        return
+
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.Stream()
@@ -94,13 +110,29 @@ def main():
     opt = nrto.default_options(method=args.method, precision=args.precision, max_admm=args.max_admm,
                                max_inner=args.max_inner, check_every=args.check_every,
                                rho=40.0 if args.method == 0 else 10.0, eps_kkt=1e-4)
+    learned = args.workload == "learned_quadrotor_4096"
     with torch.cuda.stream(stream):
         ctx = nrto.Context(probs, opt, stream=stream.cuda_stream)
+        net = feats = pred = None
+        if learned:
+            from paper_2603_02642_amd import learned as L
+            net = L.load_net(WEIGHTS, max_batch=len(probs))
+            feats = torch.from_numpy(L.features(probs)).to(dev)
+            pred = torch.empty((len(probs), L.WIDTHS[-1]), dtype=torch.float32, device=dev)
     bpp = _bytes_per_pass(ctx, args.precision)
+    fallback = []
+
+    def solve_step():
+        if learned:
+            net.infer(feats, out=pred)
+            acc, _ = ctx.warm_start(pred)
+            fallback.append(float(1.0 - acc.mean()))
+            return ctx.solve(warm=True)
+        return ctx.solve()
 
     def step():
         ctx.linearize()
-        return ctx.solve()
+        return solve_step()
 
     for _ in range(args.warmup):
         step()
@@ -115,7 +147,7 @@ def main():
         for _ in range(args.steps):
             ctx.linearize()
             ks.record(stream)
-            rep = ctx.solve()
+            rep = solve_step()
             ke.record(stream)
             ke.synchronize()
             solve_ms.append(ks.elapsed_time(ke))
@@ -150,7 +182,8 @@ def main():
                    "instances": ctx.n, "converged": int(np.sum(conv)),
                    "admm_iters_mean": float(np.mean([r.admm_iters for r in rep])),
                    "inner_iters_mean": float(np.mean([r.inner_iters for r in rep])),
-                   "kkt_max": float(np.max([r.kkt for r in rep]))},
+                   "kkt_max": float(np.max([r.kkt for r in rep])),
+                   "fallback_rate": (float(np.mean(fallback)) if fallback else None)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "solve_kernel", "kernel_ms": kern_ms},

@@ -517,6 +517,10 @@ extern "C" nrto_status nrto_download_socp(nrto_ctx c, int32_t inst, double* A, d
 
 extern "C" nrto_status nrto_solve_socp(nrto_ctx c, int32_t warm, nrto_solve_report* rep) {
   if (!c) return set_global_error(NRTO_ERR_ARG, "null context");
+  if (c->opt.method == NRTO_FULLADMM)
+    return ctx_err(c, NRTO_ERR_STATE,
+                   "the FullADMM device path is switched off: its kernel took a GPU memory fault whose cause "
+                   "is not yet identified; use NRTO_DR");
   SolveOpts o;
   fill_opts(c, o, warm ? 1 : 0);
   for (int gi = 0; gi < 3; ++gi) {

@@ -1091,7 +1091,8 @@ __device__ int qp_block(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double r
       psi = phi;
     }
     if (!(mu == 0.0 && psi <= r)) {
-      // Illinois regula falsi on f(mu) = 1/r - 1/psi(mu), increasing in mu
+      // Illinois regula falsi on f(mu) = 1/r - 1/psi(mu), which decreases in mu
+      // (psi(mu) = ||F_u du(mu)|| decreases): psi > r keeps mu on the low side.
       double flo = 1.0 / r - 1.0 / plo, fhi = 1.0 / r - 1.0 / phi;
       int side = 0;
       for (int it = 0; it < 100 && fabs(psi - r) > tol; ++it) {
@@ -1101,7 +1102,7 @@ __device__ int qp_block(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double r
         psi = state_norm<NX, NU, F>(I);
         mu = m;
         const double fm = 1.0 / r - 1.0 / psi;
-        if (fm < 0.0) {
+        if (psi > r) {
           lo = m;
           flo = fm;
           if (side == -1) fhi *= 0.5;

@@ -61,6 +61,11 @@ def test_dr_iterates_match_oracle_fp64(T, L, M, alpha):
     assert abs(rep[0].kkt - ref_kkt) <= 1e-9 * max(1.0, ref_kkt)
 
 
+FA_OFF = ("FullADMM device path switched off: its kernel took a GPU memory fault "
+          "(aperture violation) whose cause is not yet identified")
+
+
+@pytest.mark.skip(reason=FA_OFF)
 @pytest.mark.parametrize("T,L", [(8, 30), (5, 12)])
 def test_fulladmm_iterates_match_oracle_fp64(T, L):
     _torch()
@@ -87,11 +92,21 @@ def test_trust_region_active_matches_oracle():
     _torch()
     prob = synth.config1()
     s = linearize.assemble(prob, prob.u_init, 2.0)
-    o = fulladmm.Options(max_admm=6, eps_kkt=0.0)
-    st, _ = fulladmm.solve(s, o)
+    o = dr.Options(max_admm=4, max_dr=20, eps_kkt=0.0, eps_dr_abs=0.0, eps_dr_rel=0.0)
+    st, _ = dr.solve(s, o)
     assert st.mu > 0
-    c = _ctx(prob, s, method=1, max_admm=6, eps_kkt=0.0, rho=10.0, r_trust=2.0)
+    c = _ctx(prob, s, method=0, max_admm=4, max_inner=20, eps_kkt=0.0, eps_dr_abs=0.0, eps_dr_rel=0.0,
+             r_trust=2.0)
     c.solve()
     g = c.solution(0)
     assert abs(g["mu"] - st.mu) <= 1e-9 * max(1.0, st.mu)
     assert rel_err(g["du"], st.du) <= 1e-9
+
+
+def test_fulladmm_path_raises_while_switched_off():
+    _torch()
+    from paper_2603_02642_amd import nrto
+    prob = near_obstacle_problem(5)
+    c = nrto.Context([prob], nrto.default_options(method=1))
+    with pytest.raises(nrto.NrtoError):
+        c.solve()
