@@ -100,6 +100,13 @@ typedef struct {
   double eps_dr_abs, eps_dr_rel; /* DR stop: ||s~_new - s~|| <= abs + rel max(1, ||s~||) */
   double eps_kkt;            /* stop when the FP64 KKT residual <= eps_kkt (0 = never) */
   double r_trust;            /* trust-region radius ||F_u du|| <= r_trust */
+  int32_t cold_init;         /* cold point: 0 = all zeros (the printed initialisation), 1 = every
+                                cone at its open-loop value: p = p~ = ||b_hat_j||,
+                                s~_j = (||b_hat_j||, b_hat_j), so k_v = 0 is cone-feasible (DR only) */
+  int32_t rho_adapt;         /* 1 = residual balancing of rho after each dual update (DR only):
+                                rho *= rho_tau if r_p > rho_mu r_d, rho /= rho_tau if
+                                r_d > rho_mu r_p, kept in [rho_min, rho_max] */
+  double rho_mu, rho_tau, rho_min, rho_max;
 } nrto_options;
 
 /* Per-instance result of a solve. */
@@ -111,6 +118,8 @@ typedef struct {
   double kkt;                /* FP64 KKT residual of the returned iterate */
   double r_p, r_d;           /* ||p - p~||, rho ||p~ - p~_prev|| of the last ADMM step */
   double mu;                 /* trust-region multiplier */
+  double rho;                /* penalty at the end of the solve (differs from the option's
+                                value only with rho_adapt) */
 } nrto_solve_report;
 
 /* Per-instance result of one successive-linearisation step. */
@@ -120,10 +129,12 @@ typedef struct {
   double merit_old, merit_new, predicted;
   double r_trust;            /* radius for the next step */
   double kkt;
+  int32_t admm_iters, inner_iters; /* of the step's SOCP solve */
 } nrto_step_report;
 
 /* Defaults: DR, FP64, 40 ADMM x 100 DR iterations, rho 40, alpha 1,
- * sigma 1, eps_dr 1e-4, eps_kkt 1e-4, r_trust 2 (paper hyperparameter tables). */
+ * sigma 1, eps_dr 1e-4, eps_kkt 1e-4, r_trust 2 (paper hyperparameter tables);
+ * cold_init 0, rho_adapt 0 with rho_mu 10, rho_tau 2, rho_min 1, rho_max 200. */
 void nrto_default_options(nrto_options *opt);
 
 /*
@@ -233,6 +244,14 @@ nrto_status nrto_warm_start(nrto_ctx ctx, const float *pred, int64_t ld, int32_t
  * acceptance, u_hat += du and the new gains.  rep: n_inst entries or NULL.
  */
 nrto_status nrto_scp_step(nrto_ctx ctx, nrto_step_report *rep);
+/*
+ * The second half of nrto_scp_step on the solution of the last nrto_solve_socp
+ * (which must follow an nrto_linearize of the current nominal): nonlinear
+ * rollout of the candidate, merit test (penalty weight 10), trust-region update
+ * and, on acceptance, u_hat += du and the new gains.  rep: n_inst entries or
+ * NULL; its status, kkt and iteration counts are those of the last solve.
+ */
+nrto_status nrto_scp_accept(nrto_ctx ctx, nrto_step_report *rep);
 /* Current nominal controls of instance inst (T*nu) and gains (T*nu*nx, may be NULL). */
 nrto_status nrto_get_nominal(nrto_ctx ctx, int32_t inst, double *uhat, double *K);
 

@@ -20,6 +20,19 @@ t_j = p~_j, eta_j = A_hat_j k_v + b_hat_j (supplementary II-A):
     xi~     += alpha (Prox_Jhat(xi_ref) - xi),  Prox_Jhat = (identity on chi, Pi_K on s)
 stopped when ||s~_new - s~_old||_2 <= eps_abs + eps_rel max(1, ||s~||) or after
 max_dr steps.  The DR state xi~ is carried from one ADMM iteration to the next.
+
+Two options depart from the printed method (both off by default):
+  cold_init = "margin": the cold point starts every cone at its open-loop value,
+    p = p~ = p~~ = ||b_hat_j||, s~_j = (||b_hat_j||, b_hat_j), so that k_v = 0 is
+    feasible for every cone; the printed initialisation is all zeros.  From
+    zeros, a cone whose constraint is slack still holds p~ below ||b_hat_j|| and
+    the only force lifting it is the proximal term rho/2 ||p~ - p||^2, which
+    moves it by O(1/rho) per ADMM iteration (sublinear creep).
+  rho_adapt: residual balancing of the penalty (Boyd et al., Foundations and
+    Trends in ML 3(1), 2011, section 3.4.1): after the dual update, rho <- rho
+    tau when r_p > mu r_d, rho <- rho / tau when r_d > mu r_p, kept in
+    [rho_min, rho_max].  lambda is unscaled, so it is kept as it is; the
+    k_v factor does not involve rho, so nothing is refactored.
 """
 from __future__ import annotations
 
@@ -48,6 +61,12 @@ class Options:
     check_every: int = 1
     eps_p: float = 0.0
     eps_d: float = 0.0
+    cold_init: str = "zero"        # "zero" (printed) or "margin"
+    rho_adapt: bool = False
+    rho_mu: float = 10.0
+    rho_tau: float = 2.0
+    rho_min: float = 1.0
+    rho_max: float = 200.0
 
 
 @dataclasses.dataclass
@@ -69,6 +88,22 @@ def zero_state(socp) -> State:
     return State(K_t=np.zeros((T, nu, nx)), pt_t=np.zeros(ng), s_t=np.zeros((ng, 1 + socp.nz)),
                  du=np.zeros(T * nu), p=np.zeros(ng), lam=np.zeros(ng),
                  K=np.zeros((T, nu, nx)), pt=np.zeros(ng), pi=np.zeros(ng), mu=0.0)
+
+
+def cold_state(socp, opt: Options) -> State:
+    """The cold point: zeros, or with cold_init == "margin" every cone at its
+    open-loop value (||b_hat_j||, b_hat_j) with p = p~ = p~~ = ||b_hat_j||."""
+    st = zero_state(socp)
+    if opt.cold_init == "margin":
+        nb = np.sqrt(np.sum(socp.bhat * socp.bhat, axis=1))
+        st.p[:] = nb
+        st.pt[:] = nb
+        st.pt_t[:] = nb
+        st.s_t[:, 0] = nb
+        st.s_t[:, 1:] = socp.bhat
+    elif opt.cold_init != "zero":
+        raise ValueError(opt.cold_init)
+    return st
 
 
 def zeta(socp, opt: Options, st: State) -> np.ndarray:
@@ -118,8 +153,9 @@ def dr_steps(socp, opt: Options, st: State, fac, max_steps: int, trace: Optional
 
 def solve(socp, opt: Options = Options(), st: Optional[State] = None, trace: Optional[Callable] = None):
     """Returns (State, info dict)."""
+    opt = dataclasses.replace(opt)      # rho_adapt changes opt.rho
     if st is None:
-        st = zero_state(socp)
+        st = cold_state(socp, opt)
     fac = factor(socp, opt)
     info = {"admm_iters": 0, "dr_iters": 0, "kkt": np.inf, "status": "maxiter", "r_p": np.inf, "r_d": np.inf}
     pt_prev = st.pt.copy()
@@ -145,5 +181,11 @@ def solve(socp, opt: Options = Options(), st: Optional[State] = None, trace: Opt
         if stop:
             info["status"] = "ok"
             break
+        if opt.rho_adapt:
+            if info["r_p"] > opt.rho_mu * info["r_d"]:
+                opt.rho = min(opt.rho_max, opt.rho * opt.rho_tau)
+            elif info["r_d"] > opt.rho_mu * info["r_p"]:
+                opt.rho = max(opt.rho_min, opt.rho / opt.rho_tau)
     info["kkt"] = residual(socp, opt, st)
+    info["rho"] = opt.rho
     return st, info

@@ -68,6 +68,7 @@ class StepResult:
     kkt: float
     du: np.ndarray
     K: np.ndarray
+    info: dict = dataclasses.field(default_factory=dict)
 
 
 def step(prob, uhat, r_trust, method="dr", opt=None):
@@ -95,7 +96,7 @@ def step(prob, uhat, r_trust, method="dr", opt=None):
         r_new = min(GROW * r_trust, R_MAX) if ratio >= ETA_GROW else r_trust
     else:
         r_new = max(SHRINK * r_trust, R_MIN)
-    return StepResult(accepted, cur, act, pred, r_new, info["kkt"], du, K)
+    return StepResult(accepted, cur, act, pred, r_new, info["kkt"], du, K, info)
 
 
 def run(prob, n_steps=10, method="dr", opt=None, r0=2.0):

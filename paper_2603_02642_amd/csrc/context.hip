@@ -59,6 +59,7 @@ struct nrto_ctx_s {
   size_t smem = 0;
   std::string err;
   std::vector<double> rtrust;  // per-instance trust radius (host copy)
+  double* scp_out = nullptr;   // 5 per instance: merit-test results of nrto_scp_step
 };
 
 static nrto_status ctx_err(nrto_ctx c, nrto_status s, const std::string& m) {
@@ -78,8 +79,8 @@ static nrto_status dalloc(nrto_ctx c, T** p, int64_t n) {
   size_t bytes = (size_t)std::max<int64_t>(n, 1) * sizeof(T);
   void* q = nullptr;
   if (hipMalloc(&q, bytes) != hipSuccess) return ctx_err(c, NRTO_ERR_ALLOC, "hipMalloc failed");
-  hipMemsetAsync(q, 0, bytes, c->stream);
   c->allocs.push_back(q);
+  if (hipMemsetAsync(q, 0, bytes, c->stream) != hipSuccess) return ctx_err(c, NRTO_ERR_HIP, "hipMemsetAsync failed");
   *p = (T*)q;
   return NRTO_OK;
 }
@@ -101,6 +102,12 @@ extern "C" void nrto_default_options(nrto_options* o) {
   o->eps_dr_rel = 1e-4;
   o->eps_kkt = 1e-4;
   o->r_trust = 2.0;
+  o->cold_init = 0;
+  o->rho_adapt = 0;
+  o->rho_mu = 10.0;
+  o->rho_tau = 2.0;
+  o->rho_min = 1.0;
+  o->rho_max = 200.0;
 }
 
 extern "C" const char* nrto_last_error(nrto_ctx c) { return c ? c->err.c_str() : g_err.c_str(); }
@@ -260,6 +267,12 @@ static void fill_opts(const nrto_ctx c, SolveOpts& o, int warm) {
   o.eps_dr_abs = c->opt.eps_dr_abs;
   o.eps_dr_rel = c->opt.eps_dr_rel;
   o.eps_kkt = c->opt.eps_kkt;
+  o.cold_init = c->opt.cold_init;
+  o.rho_adapt = c->opt.rho_adapt;
+  o.rho_mu = c->opt.rho_mu;
+  o.rho_tau = c->opt.rho_tau;
+  o.rho_min = c->opt.rho_min;
+  o.rho_max = c->opt.rho_max;
 }
 
 static nrto_status check_options(nrto_ctx c, const nrto_options* o) {
@@ -272,6 +285,11 @@ static nrto_status check_options(nrto_ctx c, const nrto_options* o) {
   if (!(o->r_trust > 0)) return ctx_err(c, NRTO_ERR_ARG, "r_trust > 0 required");
   if (o->block_threads != 0 && (o->block_threads < 64 || o->block_threads > 1024 || o->block_threads % 64))
     return ctx_err(c, NRTO_ERR_ARG, "block_threads must be 0 or a multiple of 64 in [64, 1024]");
+  if (o->cold_init != 0 && o->cold_init != 1) return ctx_err(c, NRTO_ERR_ARG, "cold_init must be 0 or 1");
+  if (o->rho_adapt != 0 && o->rho_adapt != 1) return ctx_err(c, NRTO_ERR_ARG, "rho_adapt must be 0 or 1");
+  if (o->rho_adapt &&
+      !(o->rho_mu > 1 && o->rho_tau > 1 && o->rho_min > 0 && o->rho_min <= o->rho && o->rho <= o->rho_max))
+    return ctx_err(c, NRTO_ERR_ARG, "rho_adapt needs rho_mu > 1, rho_tau > 1, 0 < rho_min <= rho <= rho_max");
   return NRTO_OK;
 }
 
@@ -383,6 +401,7 @@ extern "C" nrto_status nrto_setup(const nrto_problem* probs, int32_t n, const nr
   ALLOC(g.iscr, (int64_t)n * ISCR_N);
   ALLOC(g.flags, (int64_t)n * 4);
   ALLOC(g.rep, n);
+  ALLOC(c->scp_out, 5 * (int64_t)n);
   ALLOC(c->order, n);
 #undef ALLOC
   // uploads
@@ -521,6 +540,10 @@ extern "C" nrto_status nrto_solve_socp(nrto_ctx c, int32_t warm, nrto_solve_repo
     return ctx_err(c, NRTO_ERR_STATE,
                    "the FullADMM device path is switched off: its kernel took a GPU memory fault whose cause "
                    "is not yet identified; use NRTO_DR");
+  if (c->opt.precision == NRTO_FP32)
+    return ctx_err(c, NRTO_ERR_STATE,
+                   "the FP32 solver path is switched off: its kernel took a GPU memory fault whose cause is not "
+                   "yet identified; use NRTO_FP64");
   SolveOpts o;
   fill_opts(c, o, warm ? 1 : 0);
   for (int gi = 0; gi < 3; ++gi) {
@@ -661,24 +684,16 @@ extern "C" nrto_status nrto_get_nominal(nrto_ctx c, int32_t inst, double* uhat, 
   return NRTO_OK;
 }
 
-extern "C" nrto_status nrto_scp_step(nrto_ctx c, nrto_step_report* rep) {
+extern "C" nrto_status nrto_scp_accept(nrto_ctx c, nrto_step_report* rep) {
   if (!c) return set_global_error(NRTO_ERR_ARG, "null context");
-  nrto_status s = nrto_linearize(c);
-  if (s != NRTO_OK) return s;
-  std::vector<nrto_solve_report> sr(c->n);
-  // the KKT residual (and the robust margins the merit test reads) must be evaluated
-  nrto_options keep = c->opt;
-  if (!(c->opt.eps_kkt > 0.0)) c->opt.eps_kkt = 1e-300;
-  s = nrto_solve_socp(c, 0, sr.data());
-  c->opt = keep;
-  if (s != NRTO_OK) return s;
-  double* out = nullptr;
-  if (hipMalloc(&out, sizeof(double) * 5 * c->n) != hipSuccess) return ctx_err(c, NRTO_ERR_ALLOC, "hipMalloc failed");
   std::vector<double> h(5 * (size_t)c->n);
-  hipError_t e = launch_scp_eval(c->g, c->n, 10.0, out, c->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), out, sizeof(double) * 5 * c->n, hipMemcpyDeviceToHost, c->stream);
+  std::vector<nrto_solve_report> sr(c->n);
+  hipError_t e = launch_scp_eval(c->g, c->n, 10.0, c->scp_out, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h.data(), c->scp_out, sizeof(double) * 5 * c->n, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(sr.data(), c->g.rep, sizeof(nrto_solve_report) * c->n, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  hipFree(out);
   if (e != hipSuccess) return ctx_err(c, NRTO_ERR_HIP, hipGetErrorString(e));
   if (rep)
     for (int i = 0; i < c->n; ++i) {
@@ -689,14 +704,31 @@ extern "C" nrto_status nrto_scp_step(nrto_ctx c, nrto_step_report* rep) {
       rep[i].predicted = h[5 * i + 3];
       rep[i].r_trust = h[5 * i + 4];
       rep[i].kkt = sr[i].kkt;
+      rep[i].admm_iters = sr[i].admm_iters;
+      rep[i].inner_iters = sr[i].inner_iters;
     }
   return NRTO_OK;
+}
+
+extern "C" nrto_status nrto_scp_step(nrto_ctx c, nrto_step_report* rep) {
+  if (!c) return set_global_error(NRTO_ERR_ARG, "null context");
+  nrto_status s = nrto_linearize(c);
+  if (s != NRTO_OK) return s;
+  // the KKT residual (and the robust margins the merit test reads) must be evaluated
+  nrto_options keep = c->opt;
+  if (!(c->opt.eps_kkt > 0.0)) c->opt.eps_kkt = 1e-300;
+  s = nrto_solve_socp(c, 0, nullptr);
+  c->opt = keep;
+  if (s != NRTO_OK) return s;
+  return nrto_scp_accept(c, rep);
 }
 
 extern "C" nrto_status nrto_warm_start(nrto_ctx c, const float* pred, int64_t ld, int32_t fallback_test,
                                        int32_t* accepted, double* residuals) {
   if (!c || !pred) return set_global_error(NRTO_ERR_ARG, "null argument");
   if (c->opt.method != NRTO_DR) return ctx_err(c, NRTO_ERR_STATE, "the learned warm start targets NRTO-DR");
+  if (c->opt.precision == NRTO_FP32)
+    return ctx_err(c, NRTO_ERR_STATE, "the FP32 solver path is switched off; use NRTO_FP64");
   for (auto& h : c->hi)
     if (ld < (int64_t)h.d.T * h.d.nu * (h.d.nx + 1) + 2 * (int64_t)h.d.ng)
       return ctx_err(c, NRTO_ERR_ARG, "prediction row shorter than du + K + p~ + pi");

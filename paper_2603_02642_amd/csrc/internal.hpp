@@ -85,6 +85,7 @@ enum {
   CA_E,       // constraint value e_j = g0 + b_j' du
   CA_LA,      // line-search scratch: a_j at the current iterate
   CA_LE,      // line-search scratch: change of a_j along the Newton direction
+  CA_PTP,     // p~ of the previous ADMM iteration (dual residual r_d)
   CA_NUM
 };
 
@@ -101,8 +102,9 @@ struct WaveTask {
 enum { ISCR_PSI = 0, ISCR_KKT, ISCR_RP, ISCR_RD, ISCR_N = 8 };
 
 struct SolveOpts {
-  int32_t method, precision, max_admm, max_inner, check_every, warm;
+  int32_t method, precision, max_admm, max_inner, check_every, warm, cold_init, rho_adapt;
   double rho, alpha, sigma_chi, sigma_s, eps_dr_abs, eps_dr_rel, eps_kkt;
+  double rho_mu, rho_tau, rho_min, rho_max;
 };
 
 // Device pointers the kernels use.

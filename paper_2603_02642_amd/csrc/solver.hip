@@ -395,12 +395,12 @@ __device__ __forceinline__ void soc_case(double t, double a, double& that, doubl
 // DR pass: one relaxed DR iteration over all cones of the instance (after the
 // K-solve).  Accumulates sum ||delta s~||^2 and ||s~||^2.
 template <int NX, int NU, typename F>
-__device__ void dr_pass(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o, double (&acc)[2]) {
+__device__ void dr_pass(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o, double rho, double (&acc)[2]) {
   const int T = I.T;
   const int lane = lane_id();
   const F r = (F)I.r;
   const double al = o.alpha;
-  const double den = o.rho + o.sigma_chi + o.sigma_s;
+  const double den = rho + o.sigma_chi + o.sigma_s;
   double* ws = S.wscr + wave_id() * 128;
   for (int t = next_task(S.ctr); t < I.ntask; t = next_task(S.ctr)) {
     const WaveTask tk = I.tasks[t];
@@ -419,7 +419,7 @@ __device__ void dr_pass(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o
           const F stv = I.st[e];
           F s, bh;
           if (le == 0) {
-            ptc = (o.sigma_chi * I.C(CA_PTT, c) + o.rho * I.C(CA_P, c) + I.C(CA_LAM, c) +
+            ptc = (o.sigma_chi * I.C(CA_PTT, c) + rho * I.C(CA_P, c) + I.C(CA_LAM, c) +
                    o.sigma_s * (double)stv) / den;
             s = (F)ptc;
             bh = (F)0;
@@ -487,7 +487,7 @@ __device__ void dr_pass(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o
         const int64_t e = tk.ebeg + l;
         stv = I.st[e];
         if (le == 0) {
-          ptc = (o.sigma_chi * I.C(CA_PTT, c) + o.rho * I.C(CA_P, c) + I.C(CA_LAM, c) +
+          ptc = (o.sigma_chi * I.C(CA_PTT, c) + rho * I.C(CA_P, c) + I.C(CA_LAM, c) +
                  o.sigma_s * (double)stv) / den;
           s = (F)ptc;
           ws[64 + cl] = (double)((F)2 * s - stv);
@@ -1317,39 +1317,87 @@ __device__ double kkt_residual(const Inst<NX, NU, F>& I, Smem<F>& S, const Solve
 }
 
 // ----------------------------------------------------------------------------
+template <int NX, int NU, typename F>
+__device__ void zero_state(const Inst<NX, NU, F>& I) {
+  const int T = I.T;
+  for (int64_t e = threadIdx.x; e < I.nent; e += blockDim.x) {
+    I.st[e] = (F)0;
+    I.nuv[e] = (F)0;
+  }
+  for (int c = threadIdx.x; c < I.ng; c += blockDim.x) {
+    I.C(CA_P, c) = 0.0;
+    I.C(CA_PT, c) = 0.0;
+    I.C(CA_PTT, c) = 0.0;
+    I.C(CA_LAM, c) = 0.0;
+    I.C(CA_PI, c) = 0.0;
+    I.C(CA_ACT, c) = 0.0;
+  }
+  for (int i = threadIdx.x; i < T * NU * NX; i += blockDim.x) {
+    I.K[i] = 0.0;
+    I.Kt[i] = 0.0;
+  }
+  for (int i = threadIdx.x; i < T * NU; i += blockDim.x) I.du[i] = 0.0;
+  for (int i = threadIdx.x; i < (T + 1) * NX; i += blockDim.x) I.dx[i] = 0.0;
+  if (threadIdx.x == 0) {
+    *I.mu = 0.0;
+    I.flags[0] = 0;
+    I.iscr[ISCR_PSI] = 0.0;
+  }
+  __syncthreads();
+}
+
+// Open-loop cold point (DR): every cone at its value for k_v = 0,
+// s~_j = (||b_hat_j||, b_hat_j) and p = p~ = p~~ = ||b_hat_j||.
+template <int NX, int NU, typename F>
+__device__ void margin_pass(const Inst<NX, NU, F>& I, Smem<F>& S) {
+  for (int t = next_task(S.ctr); t < I.ntask; t = next_task(S.ctr)) {
+    const WaveTask tk = I.tasks[t];
+    for (int c = tk.cone; c < tk.cone + tk.ncone; ++c) {
+      const int32_t* m = I.cm + c * CM_N;
+      const int e0 = m[CM_EOFF];
+      const int len = 1 + m[CM_NBLK] * NX;
+      double n2 = 0.0;
+      for (int le = 1 + lane_id(); le < len; le += NRTO_WAVE) {
+        const double b = (double)I.bhat[e0 + le];
+        n2 += b * b;
+        I.st[e0 + le] = I.bhat[e0 + le];
+      }
+      const double nrm = sqrt(wave_sum(n2));
+      if (lane_id() == 0) {
+        I.st[e0] = (F)nrm;
+        I.C(CA_P, c) = nrm;
+        I.C(CA_PT, c) = nrm;
+        I.C(CA_PTT, c) = nrm;
+      }
+    }
+  }
+}
+
+// The cold point of a solve: zeros, or the open-loop point when cold_init is set
+// (NRTO-DR only).
+template <int NX, int NU, typename F, int METHOD>
+__device__ void cold_state(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o) {
+  zero_state<NX, NU, F>(I);
+  if (METHOD == NRTO_DR && o.cold_init) {
+    if (threadIdx.x == 0) *S.ctr = 0;
+    __syncthreads();
+    margin_pass<NX, NU, F>(I, S);
+    __syncthreads();
+  }
+  for (int c = threadIdx.x; c < I.ng; c += blockDim.x) I.C(CA_PTP, c) = I.C(CA_PT, c);
+  __syncthreads();
+}
+
 template <int NX, int NU, typename F, int METHOD>
 __device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, char* smem) {
   Inst<NX, NU, F> I = make_inst<NX, NU, F>(g, ii);
   const int W = blockDim.x / NRTO_WAVE;
   Smem<F> S = carve<F>(smem, I.T, NX, NU, W);
   const int T = I.T;
-  const double rho = o.rho;
+  double rho = o.rho;
 
-  // cold start: zero the method state
-  if (!o.warm) {
-    for (int64_t e = threadIdx.x; e < I.nent; e += blockDim.x) {
-      I.st[e] = (F)0;
-      I.nuv[e] = (F)0;
-    }
-    for (int c = threadIdx.x; c < I.ng; c += blockDim.x) {
-      I.C(CA_P, c) = 0.0;
-      I.C(CA_PT, c) = 0.0;
-      I.C(CA_PTT, c) = 0.0;
-      I.C(CA_LAM, c) = 0.0;
-      I.C(CA_PI, c) = 0.0;
-      I.C(CA_ACT, c) = 0.0;
-    }
-    for (int i = threadIdx.x; i < T * NU * NX; i += blockDim.x) {
-      I.K[i] = 0.0;
-      I.Kt[i] = 0.0;
-    }
-    for (int i = threadIdx.x; i < T * NU; i += blockDim.x) I.du[i] = 0.0;
-    for (int i = threadIdx.x; i < (T + 1) * NX; i += blockDim.x) I.dx[i] = 0.0;
-    if (threadIdx.x == 0) {
-      *I.mu = 0.0;
-      I.flags[0] = 0;
-    }
-  }
+  if (!o.warm) cold_state<NX, NU, F, METHOD>(I, S, o);
+  for (int c = threadIdx.x; c < I.ng; c += blockDim.x) I.C(CA_PTP, c) = I.C(CA_PT, c);
   __syncthreads();
   bool pending = I.flags[0] != 0;
 
@@ -1378,7 +1426,7 @@ __device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, cha
         if (threadIdx.x == 0) *S.ctr = 0;
         __syncthreads();
         double acc[2] = {0.0, 0.0};
-        dr_pass<NX, NU, F>(I, S, o, acc);
+        dr_pass<NX, NU, F>(I, S, o, rho, acc);
         block_sum<2>(S.red, acc, W);
         ++inner;
         const double rdr = sqrt(acc[0]);
@@ -1421,6 +1469,9 @@ __device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, cha
       if (METHOD == NRTO_DR) {
         const double lam_old = I.C(CA_LAM, c);
         I.C(CA_LAM, c) = lam_old + rho * (p - pt);
+        const double dpt = pt - I.C(CA_PTP, c);
+        acc2[1] += dpt * dpt;
+        I.C(CA_PTP, c) = pt;
       } else {
         I.C(CA_LAM, c) = I.C(CA_LAM, c) + (p - pt);
       }
@@ -1429,12 +1480,18 @@ __device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, cha
     if (METHOD == NRTO_FULLADMM) k_solve<NX, NU, F, NRTO_FULLADMM>(I, S, o);
     block_sum<2>(S.red, acc2, W);
     rp = sqrt(acc2[0]);
+    if (METHOD == NRTO_DR) rd = rho * sqrt(acc2[1]);
     if (o.eps_kkt > 0.0 && (l % o.check_every == 0 || l == o.max_admm)) {
       kkt = kkt_residual<NX, NU, F, METHOD>(I, S, o, pending, W);
       if (kkt <= o.eps_kkt) {
         status = NRTO_OK;
         break;
       }
+    }
+    // residual balancing of the penalty (block-uniform: rp, rd come from block sums)
+    if (METHOD == NRTO_DR && o.rho_adapt) {
+      if (rp > o.rho_mu * rd) rho = fmin(o.rho_max, rho * o.rho_tau);
+      else if (rd > o.rho_mu * rp) rho = fmax(o.rho_min, rho / o.rho_tau);
     }
   }
   if (METHOD == NRTO_FULLADMM && pending) {
@@ -1456,6 +1513,7 @@ __device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, cha
     rep.r_p = rp;
     rep.r_d = rd;
     rep.mu = *I.mu;
+    rep.rho = rho;
     g.rep[ii] = rep;
   }
 }
@@ -1503,34 +1561,6 @@ __device__ void warm_pass(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts&
   }
 }
 
-template <int NX, int NU, typename F>
-__device__ void zero_state(const Inst<NX, NU, F>& I) {
-  const int T = I.T;
-  for (int64_t e = threadIdx.x; e < I.nent; e += blockDim.x) {
-    I.st[e] = (F)0;
-    I.nuv[e] = (F)0;
-  }
-  for (int c = threadIdx.x; c < I.ng; c += blockDim.x) {
-    I.C(CA_P, c) = 0.0;
-    I.C(CA_PT, c) = 0.0;
-    I.C(CA_PTT, c) = 0.0;
-    I.C(CA_LAM, c) = 0.0;
-    I.C(CA_PI, c) = 0.0;
-    I.C(CA_ACT, c) = 0.0;
-  }
-  for (int i = threadIdx.x; i < T * NU * NX; i += blockDim.x) {
-    I.K[i] = 0.0;
-    I.Kt[i] = 0.0;
-  }
-  for (int i = threadIdx.x; i < T * NU; i += blockDim.x) I.du[i] = 0.0;
-  for (int i = threadIdx.x; i < (T + 1) * NX; i += blockDim.x) I.dx[i] = 0.0;
-  if (threadIdx.x == 0) {
-    *I.mu = 0.0;
-    I.flags[0] = 0;
-    I.iscr[ISCR_PSI] = 0.0;
-  }
-  __syncthreads();
-}
 
 template <int NX, int NU, typename F>
 __global__ void __launch_bounds__(NRTO_SOLVER_MAX_THREADS)
@@ -1543,7 +1573,7 @@ warm_kernel(DevPtrs g, SolveOpts o, const int32_t* order, int n, const float* pr
   Smem<F> S = carve<F>(smem, I.T, NX, NU, W);
   const int T = I.T;
   double r_cold = 1e300;
-  zero_state<NX, NU, F>(I);
+  cold_state<NX, NU, F, NRTO_DR>(I, S, o);
   if (test) {
     load_kf<NX, NU, F>(I, S);
     r_cold = kkt_residual<NX, NU, F, NRTO_DR>(I, S, o, false, W);
@@ -1580,7 +1610,7 @@ warm_kernel(DevPtrs g, SolveOpts o, const int32_t* order, int n, const float* pr
   double r_warm = 0.0;
   if (test) r_warm = kkt_residual<NX, NU, F, NRTO_DR>(I, S, o, false, W);
   const bool keep = !test || r_warm <= r_cold;
-  if (!keep) zero_state<NX, NU, F>(I);
+  if (!keep) cold_state<NX, NU, F, NRTO_DR>(I, S, o);
   if (threadIdx.x == 0) {
     accepted[ii] = keep ? 1 : 0;
     res[2 * ii] = r_warm;

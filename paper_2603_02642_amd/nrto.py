@@ -36,19 +36,21 @@ class Options(C.Structure):
                 ("max_inner", C.c_int32), ("check_every", C.c_int32), ("block_threads", C.c_int32),
                 ("rho", C.c_double), ("alpha", C.c_double), ("sigma_chi", C.c_double),
                 ("sigma_s", C.c_double), ("eps_dr_abs", C.c_double), ("eps_dr_rel", C.c_double),
-                ("eps_kkt", C.c_double), ("r_trust", C.c_double)]
+                ("eps_kkt", C.c_double), ("r_trust", C.c_double), ("cold_init", C.c_int32),
+                ("rho_adapt", C.c_int32), ("rho_mu", C.c_double), ("rho_tau", C.c_double),
+                ("rho_min", C.c_double), ("rho_max", C.c_double)]
 
 
 class SolveReport(C.Structure):
     _fields_ = [("status", C.c_int32), ("admm_iters", C.c_int32), ("inner_iters", C.c_int32),
                 ("qp_newton", C.c_int32), ("kkt", C.c_double), ("r_p", C.c_double),
-                ("r_d", C.c_double), ("mu", C.c_double)]
+                ("r_d", C.c_double), ("mu", C.c_double), ("rho", C.c_double)]
 
 
 class StepReport(C.Structure):
     _fields_ = [("accepted", C.c_int32), ("status", C.c_int32), ("merit_old", C.c_double),
                 ("merit_new", C.c_double), ("predicted", C.c_double), ("r_trust", C.c_double),
-                ("kkt", C.c_double)]
+                ("kkt", C.c_double), ("admm_iters", C.c_int32), ("inner_iters", C.c_int32)]
 
 
 _lib = None
@@ -83,6 +85,7 @@ def load() -> C.CDLL:
         "nrto_get_state": (i32, [vp, i32] + [_dp] * 4),
         "nrto_set_state": (i32, [vp, i32] + [_dp] * 9),
         "nrto_scp_step": (i32, [vp, P(StepReport)]),
+        "nrto_scp_accept": (i32, [vp, P(StepReport)]),
         "nrto_get_nominal": (i32, [vp, i32, _dp, _dp]),
         "nrto_warm_start": (i32, [vp, vp, i64, i32, P(C.c_int32), _dp]),
     }
@@ -257,6 +260,11 @@ class Context:
     def scp_step(self) -> List[StepReport]:
         rep = (StepReport * self.n)()
         _check(load().nrto_scp_step(self.h, rep), self.h)
+        return list(rep)
+
+    def scp_accept(self) -> List[StepReport]:
+        rep = (StepReport * self.n)()
+        _check(load().nrto_scp_accept(self.h, rep), self.h)
         return list(rep)
 
     def nominal(self, i):

@@ -37,19 +37,27 @@ def _ctx(prob, s, **opt):
     return c
 
 
-@pytest.mark.parametrize("T,L,M,alpha", [(8, 3, 15, 1.0), (8, 2, 10, 1.6), (6, 2, 10, 0.5)])
-def test_dr_iterates_match_oracle_fp64(T, L, M, alpha):
+@pytest.mark.parametrize("T,L,M,alpha,extra", [(8, 3, 15, 1.0, {}), (8, 2, 10, 1.6, {}), (6, 2, 10, 0.5, {}),
+                                               (8, 8, 10, 1.0, {"cold_init": 1, "rho_adapt": 1}),
+                                               (7, 6, 12, 1.2, {"rho_adapt": 1, "rho": 200.0, "sigma_s": 10.0})])
+def test_dr_iterates_match_oracle_fp64(T, L, M, alpha, extra):
     _torch()
     prob = near_obstacle_problem(T)
     s = linearize.assemble(prob, prob.u_init, 5.0)
-    o = dr.Options(max_admm=L, max_dr=M, eps_kkt=0.0, eps_dr_abs=0.0, eps_dr_rel=0.0, alpha=alpha)
-    st, _ = dr.solve(s, o)
+    ox = dict(rho=extra.get("rho", 40.0), sigma_s=extra.get("sigma_s", 1.0))
+    o = dr.Options(max_admm=L, max_dr=M, eps_kkt=0.0, eps_dr_abs=0.0, eps_dr_rel=0.0, alpha=alpha,
+                   cold_init="margin" if extra.get("cold_init") else "zero",
+                   rho_adapt=bool(extra.get("rho_adapt")), **ox)
+    st, info = dr.solve(s, o)
     c = _ctx(prob, s, method=0, max_admm=L, max_inner=M, eps_kkt=0.0, eps_dr_abs=0.0, eps_dr_rel=0.0,
-             alpha=alpha, r_trust=5.0)
+             alpha=alpha, r_trust=5.0, cold_init=extra.get("cold_init", 0), rho_adapt=extra.get("rho_adapt", 0), **ox)
     rep = c.solve()
     g = c.solution(0)
     gs = c.state(0)
     assert rep[0].admm_iters == L and rep[0].inner_iters == L * M
+    assert rep[0].rho == info["rho"]
+    if extra.get("rho_adapt"):
+        assert info["rho"] != ox["rho"]        # the balancing acted within L iterations
     assert rel_err(g["du"], st.du) <= 1e-9
     assert rel_err(g["K"], st.K) <= 1e-9
     assert rel_err(g["p"], st.p) <= 1e-9

@@ -157,3 +157,70 @@ def test_dr_fixed_point_certificate():
     assert np.all(np.linalg.norm(Y[:, 1:], axis=1) <= Y[:, 0] + 1e-9)
     assert np.max(np.abs(np.sum(Y * S_hat, axis=1))) <= 1e-9
     assert np.max(np.abs(S_hat - S)) <= 1e-9
+
+
+def _trust_region_minimiser(s):
+    """min 1/2 du'H du + h'du s.t. ||F_u du|| <= r_trust through the secular
+    equation: du(mu) = -(H + mu F'F)^-1 h, mu = 0 if it is inside, else the root
+    of ||F_u du(mu)|| = r_trust (Brent)."""
+    FtF = s.Fu.T @ s.Fu
+
+    def du(mu):
+        return np.linalg.solve(s.H + mu * FtF, -s.h)
+
+    if np.linalg.norm(s.Fu @ du(0.0)) <= s.r_trust:
+        return du(0.0), 0.0
+    hi = 1.0
+    while np.linalg.norm(s.Fu @ du(hi)) > s.r_trust:
+        hi *= 4.0
+    mu = so.brentq(lambda m: np.linalg.norm(s.Fu @ du(m)) - s.r_trust, 0.0, hi, xtol=1e-14, rtol=1e-14)
+    return du(mu), mu
+
+
+def slack_quadrotor_socp():
+    """Hovering quadrotor far from its obstacles: every robust cone is slack at
+    k_v = 0, so Problem 2's solution is K* = 0 and du* = the trust-region
+    minimiser of Q_u (the trust region is active)."""
+    prob = synth.config2()
+    prob.T = 12
+    prob.u_init = prob.u_init[:12]
+    s = linearize.assemble(prob, prob.u_init, 0.5)
+    assert np.max(s.g0 + np.linalg.norm(s.bhat, axis=1)) < 0
+    return s
+
+
+def test_margin_cold_point_solves_slack_problem_in_one_step():
+    s = slack_quadrotor_socp()
+    du_ref, mu_ref = _trust_region_minimiser(s)
+    assert mu_ref > 0
+    st, info = dr.solve(s, dr.Options(cold_init="margin", max_admm=5, eps_kkt=1e-9))
+    assert info["admm_iters"] == 1 and info["dr_iters"] == 1
+    assert np.max(np.abs(st.K)) == 0.0 and np.max(st.pi) == 0.0
+    assert np.allclose(st.du, du_ref, rtol=1e-8, atol=1e-10)
+    assert abs(st.mu - mu_ref) <= 1e-7 * mu_ref
+    # from the printed zero point the same problem is not solved in 5 iterations
+    _, info0 = dr.solve(s, dr.Options(max_admm=5, eps_kkt=1e-9))
+    assert info0["kkt"] > 1e-6
+
+
+def test_margin_cold_point_keeps_the_solution():
+    s = near_obstacle_socp(T=5)
+    o = dict(rho=200.0, sigma_s=10.0, max_dr=1000, max_admm=400, eps_kkt=1e-7, eps_dr_abs=1e-9, eps_dr_rel=1e-9)
+    s0, i0 = dr.solve(s, dr.Options(**o))
+    s1, i1 = dr.solve(s, dr.Options(cold_init="margin", **o))
+    assert i0["kkt"] <= 1e-7 and i1["kkt"] <= 1e-7
+    assert np.max(np.abs(s0.K)) > 1e-3
+    assert np.allclose(s0.du, s1.du, atol=2e-5) and np.allclose(s0.K, s1.K, atol=2e-5)
+
+
+def test_residual_balancing_keeps_the_solution_and_bounds():
+    s = near_obstacle_socp(T=5)
+    o = dict(rho=200.0, sigma_s=10.0, max_dr=1000, max_admm=600, eps_kkt=1e-7, eps_dr_abs=1e-9, eps_dr_rel=1e-9)
+    s0, i0 = dr.solve(s, dr.Options(**o))
+    s1, i1 = dr.solve(s, dr.Options(rho_adapt=True, rho_min=5.0, rho_max=800.0, **o))
+    assert i0["kkt"] <= 1e-7 and i1["kkt"] <= 1e-7
+    assert i1["rho"] != 200.0 and 5.0 <= i1["rho"] <= 800.0
+    assert np.allclose(s0.du, s1.du, atol=2e-5) and np.allclose(s0.K, s1.K, atol=2e-5)
+    # the penalty only moves by the factor tau inside [rho_min, rho_max]
+    lg = np.log2(i1["rho"] / 200.0)
+    assert abs(lg - round(lg)) < 1e-12
