@@ -148,7 +148,7 @@ def main():
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    reports = []
+    reports, phases = [], []
     with torch.cuda.stream(stream):
         torch.cuda.synchronize()
         start.record(stream)
@@ -157,6 +157,7 @@ def main():
             ev[k][0].record(stream)
             solve()
             ev[k][1].record(stream)
+            phases.append(ctx.reports())
             reports.append(ctx.scp_accept())
         stop.record(stream)
     stop.synchronize()
@@ -189,6 +190,8 @@ def main():
                    "admm_iters_mean": float(admm.mean()), "dr_iters_mean": float(inner.mean()),
                    "max_admm": args.max_admm, "max_inner": args.max_inner,
                    "solve_ms_per_step": float(solve_ms.mean()),
+                   "workgroup_us_mean": {k: float(np.mean([getattr(r, k) for rep in phases for r in rep]))
+                                         for k in ("t_dr_us", "t_qp_us", "t_kkt_us", "t_total_us")},
                    "fallback_rate": (float(np.mean(fallback)) if fallback else None)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,

@@ -120,6 +120,9 @@ typedef struct {
   double mu;                 /* trust-region multiplier */
   double rho;                /* penalty at the end of the solve (differs from the option's
                                 value only with rho_adapt) */
+  double t_dr_us, t_qp_us, t_kkt_us, t_total_us; /* device wall-clock time of the workgroup in
+                                the DR passes with their K-solves, the (du, p) blocks, the KKT
+                                checks, and the whole solve */
 } nrto_solve_report;
 
 /* Per-instance result of one successive-linearisation step. */
@@ -252,6 +255,9 @@ nrto_status nrto_scp_step(nrto_ctx ctx, nrto_step_report *rep);
  * NULL; its status, kkt and iteration counts are those of the last solve.
  */
 nrto_status nrto_scp_accept(nrto_ctx ctx, nrto_step_report *rep);
+/* Per-instance reports of the last solve (n_inst entries, host memory), e.g. after
+ * nrto_solve_socp with rep = NULL.  Synchronises the context's stream. */
+nrto_status nrto_get_reports(nrto_ctx ctx, nrto_solve_report *rep);
 /* Current nominal controls of instance inst (T*nu) and gains (T*nu*nx, may be NULL). */
 nrto_status nrto_get_nominal(nrto_ctx ctx, int32_t inst, double *uhat, double *K);
 

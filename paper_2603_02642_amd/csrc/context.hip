@@ -60,7 +60,18 @@ struct nrto_ctx_s {
   std::string err;
   std::vector<double> rtrust;  // per-instance trust radius (host copy)
   double* scp_out = nullptr;   // 5 per instance: merit-test results of nrto_scp_step
+  double us_per_tick = 0.0;    // device wall clock period in microseconds
 };
+
+// Scale the wall-clock tick counts of device-written reports to microseconds.
+static void reports_to_us(const nrto_ctx c, nrto_solve_report* r, int n) {
+  for (int i = 0; i < n; ++i) {
+    r[i].t_dr_us *= c->us_per_tick;
+    r[i].t_qp_us *= c->us_per_tick;
+    r[i].t_kkt_us *= c->us_per_tick;
+    r[i].t_total_us *= c->us_per_tick;
+  }
+}
 
 static nrto_status ctx_err(nrto_ctx c, nrto_status s, const std::string& m) {
   if (c) c->err = m;
@@ -447,6 +458,12 @@ extern "C" nrto_status nrto_setup(const nrto_problem* probs, int32_t n, const nr
   HIPCHK(c, hipStreamSynchronize(sm));
   s = configure_launch(c);
   if (s != NRTO_OK) { g_err = c->err; nrto_destroy(c); return s; }
+  {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess &&
+        khz > 0)
+      c->us_per_tick = 1000.0 / (double)khz;
+  }
   *out = c;
   return NRTO_OK;
 }
@@ -554,6 +571,7 @@ extern "C" nrto_status nrto_solve_socp(nrto_ctx c, int32_t warm, nrto_solve_repo
   if (rep) {
     HIPCHK(c, copy_out(rep, c->g.rep, (size_t)c->n, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    reports_to_us(c, rep, c->n);
   }
   return NRTO_OK;
 }
@@ -681,6 +699,14 @@ extern "C" nrto_status nrto_get_nominal(nrto_ctx c, int32_t inst, double* uhat, 
   HIPCHK(c, copy_out(uhat, c->g.uhat + d.oU, (size_t)d.T * d.nu, c->stream));
   HIPCHK(c, copy_out(K, c->g.K + d.oK, (size_t)d.T * d.nu * d.nx, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  return NRTO_OK;
+}
+
+extern "C" nrto_status nrto_get_reports(nrto_ctx c, nrto_solve_report* rep) {
+  if (!c || !rep) return set_global_error(NRTO_ERR_ARG, "null argument");
+  HIPCHK(c, copy_out(rep, c->g.rep, (size_t)c->n, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  reports_to_us(c, rep, c->n);
   return NRTO_OK;
 }
 

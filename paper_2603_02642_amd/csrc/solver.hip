@@ -1395,6 +1395,9 @@ __device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, cha
   Smem<F> S = carve<F>(smem, I.T, NX, NU, W);
   const int T = I.T;
   double rho = o.rho;
+  // phase timers (device wall clock ticks, read by thread 0 after block barriers)
+  const long long t_start = wall_clock64();
+  long long t_dr = 0, t_qp = 0, t_kkt = 0, t_mark = 0;
 
   if (!o.warm) cold_state<NX, NU, F, METHOD>(I, S, o);
   for (int c = threadIdx.x; c < I.ng; c += blockDim.x) I.C(CA_PTP, c) = I.C(CA_PT, c);
@@ -1419,6 +1422,7 @@ __device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, cha
   double kkt = 1e300, rp = 0.0, rd = 0.0;
   for (int l = 1; l <= o.max_admm; ++l) {
     admm = l;
+    t_mark = wall_clock64();
     if (METHOD == NRTO_DR) {
       // (6a) DR iterations on the {k_v, p~} block, warm-started
       for (int i = 0; i < o.max_inner; ++i) {
@@ -1447,6 +1451,11 @@ __device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, cha
         I.C(CA_BETA, c) = I.C(CA_G0, c) + I.C(CA_PT, c) - I.C(CA_LAM, c);
     }
     __syncthreads();
+    {
+      const long long now = wall_clock64();
+      t_dr += now - t_mark;
+      t_mark = now;
+    }
     // (du, p) block on wave 0
     if (wave_id() == 0) {
       QPScratch<NX, NU> q = qp_carve<NX, NU>(S.qp);
@@ -1454,6 +1463,11 @@ __device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, cha
       if (lane_id() == 0) S.red[65] = (double)n;
     }
     __syncthreads();
+    {
+      const long long now = wall_clock64();
+      t_qp += now - t_mark;
+      t_mark = now;
+    }
     qpn += (int)S.red[65];
     // p, pi from the (du, p) solution; then the FullADMM k_v step; dual updates
     double acc2[2] = {0.0, 0.0};
@@ -1483,6 +1497,7 @@ __device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, cha
     if (METHOD == NRTO_DR) rd = rho * sqrt(acc2[1]);
     if (o.eps_kkt > 0.0 && (l % o.check_every == 0 || l == o.max_admm)) {
       kkt = kkt_residual<NX, NU, F, METHOD>(I, S, o, pending, W);
+      t_kkt += wall_clock64() - t_mark;
       if (kkt <= o.eps_kkt) {
         status = NRTO_OK;
         break;
@@ -1514,6 +1529,11 @@ __device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, cha
     rep.r_d = rd;
     rep.mu = *I.mu;
     rep.rho = rho;
+    // ticks here; the host scales them to microseconds
+    rep.t_dr_us = (double)t_dr;
+    rep.t_qp_us = (double)t_qp;
+    rep.t_kkt_us = (double)t_kkt;
+    rep.t_total_us = (double)(wall_clock64() - t_start);
     g.rep[ii] = rep;
   }
 }

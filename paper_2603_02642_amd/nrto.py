@@ -44,7 +44,9 @@ class Options(C.Structure):
 class SolveReport(C.Structure):
     _fields_ = [("status", C.c_int32), ("admm_iters", C.c_int32), ("inner_iters", C.c_int32),
                 ("qp_newton", C.c_int32), ("kkt", C.c_double), ("r_p", C.c_double),
-                ("r_d", C.c_double), ("mu", C.c_double), ("rho", C.c_double)]
+                ("r_d", C.c_double), ("mu", C.c_double), ("rho", C.c_double),
+                ("t_dr_us", C.c_double), ("t_qp_us", C.c_double), ("t_kkt_us", C.c_double),
+                ("t_total_us", C.c_double)]
 
 
 class StepReport(C.Structure):
@@ -86,6 +88,7 @@ def load() -> C.CDLL:
         "nrto_set_state": (i32, [vp, i32] + [_dp] * 9),
         "nrto_scp_step": (i32, [vp, P(StepReport)]),
         "nrto_scp_accept": (i32, [vp, P(StepReport)]),
+        "nrto_get_reports": (i32, [vp, P(SolveReport)]),
         "nrto_get_nominal": (i32, [vp, i32, _dp, _dp]),
         "nrto_warm_start": (i32, [vp, vp, i64, i32, P(C.c_int32), _dp]),
     }
@@ -260,6 +263,11 @@ class Context:
     def scp_step(self) -> List[StepReport]:
         rep = (StepReport * self.n)()
         _check(load().nrto_scp_step(self.h, rep), self.h)
+        return list(rep)
+
+    def reports(self) -> List[SolveReport]:
+        rep = (SolveReport * self.n)()
+        _check(load().nrto_get_reports(self.h, rep), self.h)
         return list(rep)
 
     def scp_accept(self) -> List[StepReport]:
