@@ -192,6 +192,8 @@ def main():
                    "solve_ms_per_step": float(solve_ms.mean()),
                    "workgroup_us_mean": {k: float(np.mean([getattr(r, k) for rep in phases for r in rep]))
                                          for k in ("t_dr_us", "t_qp_us", "t_kkt_us", "t_total_us")},
+                   "riccati_per_admm": float(sum(r.qp_newton for rep in phases for r in rep) /
+                                             max(1, sum(r.admm_iters for rep in phases for r in rep))),
                    "fallback_rate": (float(np.mean(fallback)) if fallback else None)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,

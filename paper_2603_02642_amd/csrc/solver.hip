@@ -1056,70 +1056,86 @@ __device__ void rollout_dx(const Inst<NX, NU, F>& I) {
 
 template <int NX, int NU, typename F>
 __device__ int qp_block(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double rho) {
+  // Trust-region multiplier: mu = 0 if psi(0) = ||F_u du(0)|| <= r, else the
+  // root of phi(mu) = 1/r - 1/psi(mu), which increases with mu and is close to
+  // linear in it (exactly so when F_u'F_u acts on one eigen-direction of the
+  // Hessian).  Safeguarded secant on phi, started from the last multiplier of
+  // this instance: a bracket lo < mu* < hi (psi(lo) > r > psi(hi)) is kept once
+  // found, steps leaving it become regula falsi / bisection steps, and while no
+  // upper end is known the multiplier grows by at most 16x per step.
   const double r = I.r_trust;
-  double mu = *I.mu;
-  rollout_dx<NX, NU, F>(I);
-  int solves = ssn<NX, NU, F>(I, q, rho, mu);
-  double psi = state_norm<NX, NU, F>(I);
   const double tol = 1e-13 * r;
-  if (!(fabs(psi - r) <= tol) && !(mu == 0.0 && psi <= r)) {
-    double lo, hi, plo, phi;
-    if (psi <= r) {
-      hi = mu;
-      phi = psi;
-      solves += ssn<NX, NU, F>(I, q, rho, 0.0);
-      psi = state_norm<NX, NU, F>(I);
-      mu = 0.0;
-      lo = 0.0;
-      plo = psi;
-    } else {
-      lo = mu;
-      plo = psi;
-      hi = fmax(2.0 * mu, 1.0);
-      solves += ssn<NX, NU, F>(I, q, rho, hi);
-      phi = state_norm<NX, NU, F>(I);
-      int guard = 0;
-      while (phi > r && guard < 80) {
-        lo = hi;
-        plo = phi;
-        hi *= 4.0;
-        solves += ssn<NX, NU, F>(I, q, rho, hi);
-        phi = state_norm<NX, NU, F>(I);
-        ++guard;
-      }
-      mu = hi;
-      psi = phi;
+  int solves = 0;
+  rollout_dx<NX, NU, F>(I);
+  auto eval = [&](double m) {
+    solves += ssn<NX, NU, F>(I, q, rho, m);
+    return state_norm<NX, NU, F>(I);
+  };
+  // start: the current multiplier, else the last positive one of this instance
+  // (kept across solves), else 1; mu = 0 is tried only when psi(start) < r
+  double mu = *I.mu;
+  if (!(mu > 0.0)) mu = (I.iscr[ISCR_MUHINT] > 0.0) ? I.iscr[ISCR_MUHINT] : 1.0;
+  double psi = eval(mu);
+  double lo = 0.0, flo = 0.0, hi = -1.0, fhi = 0.0;   // hi < 0: no upper end yet
+  bool have_lo = false;
+  double m0 = 0.0, f0 = 0.0, m1 = mu, f1 = 1.0 / r - 1.0 / psi;
+  bool have_prev = false;
+  bool done = fabs(psi - r) <= tol;
+  if (!done && psi < r) {
+    // the root lies below the last multiplier, possibly at mu = 0
+    hi = mu;
+    fhi = f1;
+    m0 = m1;
+    f0 = f1;
+    have_prev = true;
+    psi = eval(0.0);
+    m1 = 0.0;
+    f1 = 1.0 / r - 1.0 / psi;
+    mu = 0.0;
+    done = psi <= r + tol;
+  }
+  if (!done) {
+    if (psi > r) {
+      lo = m1;
+      flo = f1;
+      have_lo = true;
     }
-    if (!(mu == 0.0 && psi <= r)) {
-      // Illinois regula falsi on f(mu) = 1/r - 1/psi(mu), which decreases in mu
-      // (psi(mu) = ||F_u du(mu)|| decreases): psi > r keeps mu on the low side.
-      double flo = 1.0 / r - 1.0 / plo, fhi = 1.0 / r - 1.0 / phi;
-      int side = 0;
-      for (int it = 0; it < 100 && fabs(psi - r) > tol; ++it) {
-        double m = hi - fhi * (hi - lo) / (fhi - flo);
-        if (!(m > lo && m < hi)) m = 0.5 * (lo + hi);
-        solves += ssn<NX, NU, F>(I, q, rho, m);
-        psi = state_norm<NX, NU, F>(I);
-        mu = m;
-        const double fm = 1.0 / r - 1.0 / psi;
-        if (psi > r) {
-          lo = m;
-          flo = fm;
-          if (side == -1) fhi *= 0.5;
-          side = -1;
-        } else {
-          hi = m;
-          fhi = fm;
-          if (side == 1) flo *= 0.5;
-          side = 1;
-        }
-        if (hi - lo <= 1e-15 * hi) break;
+    for (int it = 0; it < 80; ++it) {
+      double m2;
+      if (have_prev && f1 != f0) m2 = m1 - f1 * (m1 - m0) / (f1 - f0);
+      else m2 = (m1 > 0.0) ? m1 * psi / r : 1.0;   // phi linear in mu with zero offset
+      if (hi > 0.0) {
+        if (!(m2 > lo && m2 < hi)) m2 = lo - flo * (hi - lo) / (fhi - flo);
+        if (!(m2 > lo && m2 < hi)) m2 = 0.5 * (lo + hi);
+      } else {
+        const double base = fmax(lo, 1.0);
+        if (!(m2 > lo)) m2 = 4.0 * base;
+        if (m2 > 16.0 * base) m2 = 16.0 * base;
       }
+      m0 = m1;
+      f0 = f1;
+      have_prev = true;
+      m1 = m2;
+      psi = eval(m1);
+      f1 = 1.0 / r - 1.0 / psi;
+      mu = m1;
+      if (fabs(psi - r) <= tol) break;
+      if (psi > r) {
+        lo = m1;
+        flo = f1;
+        have_lo = true;
+      } else {
+        hi = m1;
+        fhi = f1;
+      }
+      if (hi > 0.0 && hi - lo <= 1e-15 * hi) break;
     }
   }
+  (void)have_lo;
   if (lane_id() == 0) {
     *I.mu = mu;
     I.iscr[ISCR_PSI] = psi;
+    if (mu > 0.0) I.iscr[ISCR_MUHINT] = mu;
   }
   wave_sync();
   return solves;
