@@ -179,8 +179,8 @@ static nrto_status build_instance(nrto_ctx c, const nrto_problem& p, HostInst& h
   const int ng = (int)(cm.size() / CM_N);
   tlc[T] = ng;
   for (int i = 0; i < ng; ++i)
-    if (1 + cm[i * CM_N + CM_NBLK] * nx > 64 * 16)
-      return ctx_err(c, NRTO_ERR_ARG, "cone longer than 1024 entries (reduce T)");
+    if (c->opt.method == NRTO_FULLADMM && 1 + cm[i * CM_N + CM_NBLK] * nx > 64 * 16)
+      return ctx_err(c, NRTO_ERR_ARG, "FullADMM: cone longer than 1024 entries (reduce T)");
   // wave tasks: long cones alone, short consecutive cones packed up to 64 entries
   std::vector<WaveTask> longt, shortt;
   std::vector<uint64_t> shortm;

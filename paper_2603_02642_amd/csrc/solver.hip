@@ -49,7 +49,8 @@ struct Smem {
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
 __host__ __device__ inline size_t qp_scratch_doubles(int nx, int nu) {
-  return 2 * nx * nx + nx + nx * nu + 2 * nu * nu + nu * nx + nu + 2 * nx + 64;
+  return 2 * nx * nx + nx + nx * nu + 2 * nu * nu + nu * nx + nu + 2 * nx + 64 +
+         2 * (nx * nx + nx * nu) + nu * (nx + 1) + nx * nx + nu * nu + nx;
 }
 
 __host__ __device__ inline size_t smem_bytes(int T, int nx, int nu, int fbytes, int W) {
@@ -405,64 +406,59 @@ __device__ void dr_pass(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o
   for (int t = next_task(S.ctr); t < I.ntask; t = next_task(S.ctr)) {
     const WaveTask tk = I.tasks[t];
     if (tk.ncone == 1 && tk.len > NRTO_WAVE) {
-      // one long cone, EMAX entries per lane
+      // one long cone: pass 1 forms s = (p~, eta(K)) and the norm of the reflected
+      // eta; pass 2 recomputes s (no per-lane arrays), projects, relaxes and
+      // accumulates the adjoint
       const int c = tk.cone;
       const int32_t* m = I.cm + c * CM_N;
-      F sv[EMAX], tv[EMAX], hv[EMAX];
-      double sq = 0.0, ptc = 0.0;
-#pragma unroll
-      for (int i = 0; i < EMAX; ++i) {
-        const int le = lane + i * NRTO_WAVE;
-        sv[i] = tv[i] = hv[i] = (F)0;
-        if (le < tk.len) {
-          const int64_t e = tk.ebeg + le;
-          const F stv = I.st[e];
-          F s, bh;
-          if (le == 0) {
-            ptc = (o.sigma_chi * I.C(CA_PTT, c) + rho * I.C(CA_P, c) + I.C(CA_LAM, c) +
-                   o.sigma_s * (double)stv) / den;
-            s = (F)ptc;
-            bh = (F)0;
-          } else {
-            int k, x, b;
-            entry_block<NX>(m, le, k, x, b);
-            bh = I.bhat[e];
-            s = r * fwd_gemm<NX, NU, F>(I, S, T, k, x, I.bvec + (int64_t)b * NU) + bh;
-            const F sr = (F)2 * s - stv;
-            sq += (double)sr * (double)sr;
-          }
-          sv[i] = s;
-          tv[i] = stv;
-          hv[i] = bh;
+      double sq = 0.0, ptc = 0.0, tr0 = 0.0;
+      for (int le = lane; le < tk.len; le += NRTO_WAVE) {
+        const int64_t e = tk.ebeg + le;
+        const F stv = I.st[e];
+        if (le == 0) {
+          ptc = (o.sigma_chi * I.C(CA_PTT, c) + rho * I.C(CA_P, c) + I.C(CA_LAM, c) +
+                 o.sigma_s * (double)stv) / den;
+          tr0 = (double)((F)2 * (F)ptc - stv);
+        } else {
+          int k, x, b;
+          entry_block<NX>(m, le, k, x, b);
+          const F s = r * fwd_gemm<NX, NU, F>(I, S, T, k, x, I.bvec + (int64_t)b * NU) + I.bhat[e];
+          const F sr = (F)2 * s - stv;
+          sq += (double)sr * (double)sr;
         }
       }
       const double a = sqrt(wave_sum(sq));
-      const double tref = __shfl((double)((F)2 * sv[0] - tv[0]), 0, NRTO_WAVE);
+      const double tref = __shfl(tr0, 0, NRTO_WAVE);
       double that, scale;
       soc_case(tref, a, that, scale);
       double dsum = 0.0, nsum = 0.0;
-#pragma unroll
-      for (int i = 0; i < EMAX; ++i) {
-        const int le = lane + i * NRTO_WAVE;
-        if (le < tk.len) {
-          const int64_t e = tk.ebeg + le;
-          const F sr = (F)2 * sv[i] - tv[i];
-          const F shat = (le == 0) ? (F)that : (F)(scale * (double)sr);
-          const F diff = shat - sv[i];
-          const F stn = tv[i] + (F)al * diff;
-          I.st[e] = stn;
-          const double dd = al * (double)diff;
-          dsum += dd * dd;
-          nsum += (double)stn * (double)stn;
-          if (le == 0) {
-            I.C(CA_PT, c) = ptc;
-            const double pt0 = I.C(CA_PTT, c);
-            I.C(CA_PTT, c) = pt0 + al * (ptc - pt0);
-          } else {
-            int k, x, b;
-            entry_block<NX>(m, le, k, x, b);
-            adj_gemm<NX, NU, F>(S, T, k, x, I.bvec + (int64_t)b * NU, stn - hv[i]);
-          }
+      for (int le = lane; le < tk.len; le += NRTO_WAVE) {
+        const int64_t e = tk.ebeg + le;
+        const F stv = I.st[e];
+        F s, shat, bh = (F)0;
+        int k = 0, x = 0, b = 0;
+        if (le == 0) {
+          s = (F)ptc;
+          shat = (F)that;
+        } else {
+          entry_block<NX>(m, le, k, x, b);
+          bh = I.bhat[e];
+          s = r * fwd_gemm<NX, NU, F>(I, S, T, k, x, I.bvec + (int64_t)b * NU) + bh;
+          const F sr = (F)2 * s - stv;
+          shat = (F)(scale * (double)sr);
+        }
+        const F diff = shat - s;
+        const F stn = stv + (F)al * diff;
+        I.st[e] = stn;
+        const double dd = al * (double)diff;
+        dsum += dd * dd;
+        nsum += (double)stn * (double)stn;
+        if (le == 0) {
+          I.C(CA_PT, c) = ptc;
+          const double pt0 = I.C(CA_PTT, c);
+          I.C(CA_PTT, c) = pt0 + al * (ptc - pt0);
+        } else {
+          adj_gemm<NX, NU, F>(S, T, k, x, I.bvec + (int64_t)b * NU, stn - bh);
         }
       }
       acc[0] += dsum;
@@ -695,6 +691,9 @@ __device__ void fa_commit(const Inst<NX, NU, F>& I, Smem<F>& S) {
 template <int NX, int NU>
 struct QPScratch {
   double *V, *v, *PA, *PB, *Huu, *Hux, *hu, *L, *tmp, *red;
+  double* AB[2];   // double buffer of one stage's A (NX*NX) and B (NX*NU)
+  double* G;       // gains of the current stage, NU*(NX+1)
+  double *Qs, *Rs, *xg;   // LDS copies of Q, Ru, the goal state
 };
 
 template <int NX, int NU>
@@ -709,26 +708,87 @@ __device__ QPScratch<NX, NU> qp_carve(double* q) {
   s.hu = q; q += NU;
   s.L = q; q += NU * NU;
   s.tmp = q; q += 2 * NX;
-  s.red = q;
+  s.red = q; q += 64;
+  s.AB[0] = q; q += NX * NX + NX * NU;
+  s.AB[1] = q; q += NX * NX + NX * NU;
+  s.G = q; q += NU * (NX + 1);
+  s.Qs = q; q += NX * NX;
+  s.Rs = q; q += NU * NU;
+  s.xg = q;
   return s;
 }
 
+// Active-set flags of one stage, loaded a stage ahead: lane l holds the flag of
+// state cone tls[t] + l and of control cone tlc[k] + l (cones beyond the first 64
+// of a stage are read directly when used).
+struct StageFlags {
+  int s0, s1, c0, c1;
+  bool sf, cf;
+  template <class InstT>
+  __device__ void load(const InstT& I, int t, int k) {
+    s0 = I.tls[t];
+    s1 = I.tls[t + 1];
+    const int l = lane_id();
+    sf = (s0 + l < s1) && I.C(CA_ACT, s0 + l) != 0.0;
+    if (k >= 0) {
+      c0 = I.tlc[k];
+      c1 = I.tlc[k + 1];
+      cf = (c0 + l < c1) && I.C(CA_ACT, c0 + l) != 0.0;
+    } else {
+      c0 = c1 = 0;
+      cf = false;
+    }
+  }
+};
+
 // Add the active state-constraint terms of time t to (V, v): rho w w', rho beta w.
 template <int NX, int NU, typename F>
-__device__ void add_state_terms(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, int t, double rho) {
+__device__ void add_state_terms(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, const StageFlags& fl, double rho) {
   const int lane = lane_id();
-  const int c0 = I.tls[t], c1 = I.tls[t + 1];
-  for (int c = c0; c < c1; ++c) {
-    if (I.C(CA_ACT, c) == 0.0) continue;
-    const double* w = I.W + (int64_t)c * NX;
-    const double be = I.C(CA_BETA, c);
-    for (int idx = lane; idx < NX * NX; idx += NRTO_WAVE) {
-      const int i = idx / NX, j = idx - i * NX;
-      q.V[idx] += rho * w[i] * w[j];
+  uint64_t mask = __ballot(fl.sf);
+  for (int base = fl.s0; base < fl.s1; base += NRTO_WAVE) {
+    if (base > fl.s0) mask = __ballot((base + lane < fl.s1) && I.C(CA_ACT, base + lane) != 0.0);
+    while (mask) {
+      const int bit = __ffsll((unsigned long long)mask) - 1;
+      mask &= mask - 1;
+      const int c = base + bit;
+      const double* w = I.W + (int64_t)c * NX;
+      const double be = I.C(CA_BETA, c);
+      if (lane < NX) q.tmp[lane] = w[lane];
+      wave_sync();
+      for (int idx = lane; idx < NX * NX; idx += NRTO_WAVE) {
+        const int i = idx / NX, j = idx - i * NX;
+        q.V[idx] += rho * q.tmp[i] * q.tmp[j];
+      }
+      if (lane < NX) q.v[lane] += rho * be * q.tmp[lane];
+      wave_sync();
     }
-    if (lane < NX) q.v[lane] += rho * be * w[lane];
   }
 }
+
+// Stage data of the Riccati passes: A_k (NX*NX) then B_k (NX*NU), staged in LDS
+// one stage ahead (each lane holds its share of the next stage in registers
+// while the current stage is computed).
+template <int NX, int NU>
+struct StagePrefetch {
+  static constexpr int N = NX * NX + NX * NU;
+  static constexpr int PER = (N + NRTO_WAVE - 1) / NRTO_WAVE;
+  double v[PER];
+  __device__ void load(const double* A, const double* B) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int idx = lane_id() + i * NRTO_WAVE;
+      v[i] = (idx < NX * NX) ? A[idx] : ((idx < N) ? B[idx - NX * NX] : 0.0);
+    }
+  }
+  __device__ void store(double* dst) const {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int idx = lane_id() + i * NRTO_WAVE;
+      if (idx < N) dst[idx] = v[i];
+    }
+  }
+};
 
 // Riccati solve of the LQ problem of the current active set at multiplier mu;
 // result in (du2, dx2).
@@ -736,22 +796,38 @@ template <int NX, int NU, typename F>
 __device__ void riccati(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double rho, double mu) {
   const int lane = lane_id();
   const int T = I.T;
+  StagePrefetch<NX, NU> pf;
+  StageFlags fl, fln;
+  pf.load(I.A + (int64_t)(T - 1) * NX * NX, I.B + (int64_t)(T - 1) * NX * NU);
+  fl.load(I, T, -1);
+  fln.load(I, T - 1, T - 1);
+  // LDS copies of the stage-invariant cost data
+  for (int idx = lane; idx < NX * NX; idx += NRTO_WAVE) q.Qs[idx] = I.Q[idx];
+  for (int idx = lane; idx < NU * NU; idx += NRTO_WAVE) q.Rs[idx] = I.Ru[idx];
+  if (lane < NX) q.xg[lane] = I.xg[lane];
+  wave_sync();
   // terminal cost-to-go
   for (int idx = lane; idx < NX * NX; idx += NRTO_WAVE) {
     const int i = idx / NX, j = idx - i * NX;
-    q.V[idx] = 2.0 * I.Q[idx] + (i == j ? mu : 0.0);
+    q.V[idx] = 2.0 * q.Qs[idx] + (i == j ? mu : 0.0);
   }
   if (lane < NX) {
     double s = 0.0;
-    for (int j = 0; j < NX; ++j) s += I.Q[lane * NX + j] * (I.xhat[T * NX + j] - I.xg[j]);
+    for (int j = 0; j < NX; ++j) s += q.Qs[lane * NX + j] * (I.xhat[T * NX + j] - q.xg[j]);
     q.v[lane] = 2.0 * s;
   }
+  pf.store(q.AB[(T - 1) & 1]);
   wave_sync();
-  add_state_terms<NX, NU, F>(I, q, T, rho);
+  add_state_terms<NX, NU, F>(I, q, fl, rho);
   wave_sync();
   for (int k = T - 1; k >= 0; --k) {
-    const double* A = I.A + (int64_t)k * NX * NX;
-    const double* B = I.B + (int64_t)k * NX * NU;
+    const double* A = q.AB[k & 1];
+    const double* B = A + NX * NX;
+    fl = fln;
+    if (k > 0) {
+      pf.load(I.A + (int64_t)(k - 1) * NX * NX, I.B + (int64_t)(k - 1) * NX * NU);
+      fln.load(I, k - 1, k - 1);
+    }
     for (int idx = lane; idx < NX * NX; idx += NRTO_WAVE) {
       const int i = idx / NX, j = idx - i * NX;
       double s = 0.0;
@@ -769,7 +845,7 @@ __device__ void riccati(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double r
     wave_sync();
     for (int idx = lane; idx < NU * NU; idx += NRTO_WAVE) {
       const int u = idx / NU, w = idx - u * NU;
-      double s = 2.0 * I.Ru[idx];
+      double s = 2.0 * q.Rs[idx];
 #pragma unroll
       for (int i = 0; i < NX; ++i) s += B[i * NU + u] * q.PB[i * NU + w];
       q.Huu[idx] = s;
@@ -784,23 +860,36 @@ __device__ void riccati(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double r
     if (lane < NU) {
       double s = 0.0;
 #pragma unroll
-      for (int w = 0; w < NU; ++w) s += I.Ru[lane * NU + w] * I.uhat[k * NU + w];
+      for (int w = 0; w < NU; ++w) s += q.Rs[lane * NU + w] * I.uhat[k * NU + w];
       s *= 2.0;
 #pragma unroll
       for (int i = 0; i < NX; ++i) s += B[i * NU + lane] * q.v[i];
       q.hu[lane] = s;
     }
     wave_sync();
-    if (lane == 0) {
-      for (int c = I.tlc[k]; c < I.tlc[k + 1]; ++c) {
-        if (I.C(CA_ACT, c) == 0.0) continue;
-        const int32_t* m = I.cm + c * CM_N;
-        const int i = m[CM_CIDX];
-        q.Huu[i * NU + i] += rho;
-        q.hu[i] += rho * I.C(CA_BETA, c) * (double)m[CM_CSIGN];
+    {
+      // active control bounds of stage k (flags prefetched a stage ahead)
+      uint64_t cmask = __ballot(fl.cf);
+      if (lane == 0) {
+        for (int base = fl.c0; base < fl.c1; base += NRTO_WAVE) {
+          if (base > fl.c0) {
+            cmask = 0;
+            for (int b = 0; b < NRTO_WAVE && base + b < fl.c1; ++b)
+              if (I.C(CA_ACT, base + b) != 0.0) cmask |= 1ull << b;
+          }
+          while (cmask) {
+            const int bit = __ffsll((unsigned long long)cmask) - 1;
+            cmask &= cmask - 1;
+            const int c = base + bit;
+            const int32_t* m = I.cm + c * CM_N;
+            const int i = m[CM_CIDX];
+            q.Huu[i * NU + i] += rho;
+            q.hu[i] += rho * I.C(CA_BETA, c) * (double)m[CM_CSIGN];
+          }
+        }
+        for (int i = 0; i < NU * NU; ++i) q.L[i] = q.Huu[i];
+        chol_inplace<NU>(q.L);
       }
-      for (int i = 0; i < NU * NU; ++i) q.L[i] = q.Huu[i];
-      chol_inplace<NU>(q.L);
     }
     wave_sync();
     double* gk = I.ric + (int64_t)k * NU * (NX + 1);
@@ -810,7 +899,10 @@ __device__ void riccati(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double r
       for (int u = 0; u < NU; ++u) z[u] = (lane < NX) ? q.Hux[u * NX + lane] : q.hu[u];
       chol_solve<NU>(q.L, z);
 #pragma unroll
-      for (int u = 0; u < NU; ++u) gk[u * (NX + 1) + lane] = -z[u];
+      for (int u = 0; u < NU; ++u) {
+        gk[u * (NX + 1) + lane] = -z[u];
+        q.G[u * (NX + 1) + lane] = -z[u];
+      }
     }
     wave_sync();
     if (k > 0) {
@@ -818,42 +910,48 @@ __device__ void riccati(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double r
       int n = 0;
       for (int idx = lane; idx < NX * NX; idx += NRTO_WAVE, ++n) {
         const int i = idx / NX, j = idx - i * NX;
-        double s = 2.0 * I.Q[idx] + (i == j ? mu : 0.0);
+        double s = 2.0 * q.Qs[idx] + (i == j ? mu : 0.0);
 #pragma unroll
         for (int l = 0; l < NX; ++l) s += A[l * NX + i] * q.PA[l * NX + j];
 #pragma unroll
-        for (int u = 0; u < NU; ++u) s += q.Hux[u * NX + i] * gk[u * (NX + 1) + j];
+        for (int u = 0; u < NU; ++u) s += q.Hux[u * NX + i] * q.G[u * (NX + 1) + j];
         nv[n] = s;
       }
       double vv = 0.0;
       if (lane < NX) {
         double s = 0.0;
-        for (int j = 0; j < NX; ++j) s += I.Q[lane * NX + j] * (I.xhat[k * NX + j] - I.xg[j]);
+        for (int j = 0; j < NX; ++j) s += q.Qs[lane * NX + j] * (I.xhat[k * NX + j] - q.xg[j]);
         s *= 2.0;
 #pragma unroll
         for (int l = 0; l < NX; ++l) s += A[l * NX + lane] * q.v[l];
 #pragma unroll
-        for (int u = 0; u < NU; ++u) s += q.Hux[u * NX + lane] * gk[u * (NX + 1) + NX];
+        for (int u = 0; u < NU; ++u) s += q.Hux[u * NX + lane] * q.G[u * (NX + 1) + NX];
         vv = s;
       }
       wave_sync();
       n = 0;
       for (int idx = lane; idx < NX * NX; idx += NRTO_WAVE, ++n) q.PA[idx] = nv[n];
       if (lane < NX) q.v[lane] = vv;
+      pf.store(q.AB[(k - 1) & 1]);
       wave_sync();
       for (int idx = lane; idx < NX * NX; idx += NRTO_WAVE) {
         const int i = idx / NX, j = idx - i * NX;
         q.V[idx] = 0.5 * (q.PA[i * NX + j] + q.PA[j * NX + i]);
       }
       wave_sync();
-      add_state_terms<NX, NU, F>(I, q, k, rho);
+      add_state_terms<NX, NU, F>(I, q, fl, rho);
       wave_sync();
     }
   }
-  // forward rollout from dx_0 = 0
+  // forward rollout from dx_0 = 0; the stage's A, B are staged in LDS one stage ahead
   if (lane < NX) I.dx2[lane] = 0.0;
+  pf.load(I.A, I.B);
+  pf.store(q.AB[0]);
   wave_sync();
   for (int k = 0; k < T; ++k) {
+    const double* A = q.AB[k & 1];
+    const double* B = A + NX * NX;
+    if (k + 1 < T) pf.load(I.A + (int64_t)(k + 1) * NX * NX, I.B + (int64_t)(k + 1) * NX * NU);
     const double* gk = I.ric + (int64_t)k * NU * (NX + 1);
     const double* xk = I.dx2 + (int64_t)k * NX;
     if (lane < NU) {
@@ -864,8 +962,6 @@ __device__ void riccati(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double r
     }
     wave_sync();
     if (lane < NX) {
-      const double* A = I.A + (int64_t)k * NX * NX;
-      const double* B = I.B + (int64_t)k * NX * NU;
       double s = 0.0;
 #pragma unroll
       for (int j = 0; j < NX; ++j) s += A[lane * NX + j] * xk[j];
@@ -873,6 +969,7 @@ __device__ void riccati(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double r
       for (int u = 0; u < NU; ++u) s += B[lane * NU + u] * I.du2[k * NU + u];
       I.dx2[(k + 1) * NX + lane] = s;
     }
+    if (k + 1 < T) pf.store(q.AB[(k + 1) & 1]);
     wave_sync();
   }
 }
