@@ -36,8 +36,9 @@ WEIGHTS = os.path.join(ROOT, "paper_2603_02642_amd", "weights", "ws_quadrotor_T5
 
 HBM_PEAK_GBS = 8000.0
 
-# NRTO-DR settings of the benchmark: open-loop cold point, rho 200, sigma_s 100
-TUNED = dict(rho=200.0, sigma_s=100.0, cold_init=1)
+# NRTO-DR settings of the benchmark: open-loop cold point, rho 200, sigma_s from 100 balanced
+# every 10 DR iterations (threshold 2)
+TUNED = dict(rho=200.0, sigma_s=100.0, cold_init=1, sigma_adapt=1, sigma_thr=2.0)
 
 
 def _problems(name, n=None):
@@ -69,7 +70,7 @@ def cpu_baseline(name, args):
     from oracle import dr, scp
     prob = _problems(name, 2)[0]
     o = dr.Options(max_admm=args.max_admm, max_dr=args.max_inner, eps_kkt=1e-4, rho=TUNED["rho"],
-                   sigma_s=TUNED["sigma_s"], cold_init="margin")
+                   sigma_s=TUNED["sigma_s"], cold_init="margin", sigma_adapt=True, sigma_thr=TUNED["sigma_thr"])
     t0 = time.perf_counter()
     res = scp.step(prob, prob.u_init, 2.0, "dr", o)
     dt = time.perf_counter() - t0

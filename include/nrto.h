@@ -107,6 +107,18 @@ typedef struct {
                                 rho *= rho_tau if r_p > rho_mu r_d, rho /= rho_tau if
                                 r_d > rho_mu r_p, kept in [rho_min, rho_max] */
   double rho_mu, rho_tau, rho_min, rho_max;
+  int32_t sigma_adapt;       /* 1 = balance the DR scaling sigma_s during the solve (DR only):
+                                after every sigma_every-th DR iteration, with S the affine point,
+                                S_hat its projection and K~ the gain state before the iteration,
+                                ratio = sqrt((||S_hat - S|| / max(1, ||S||)) /
+                                             (||K - K~|| / max(1, ||K||))), skipped while
+                                either residual is below 1e-9 of its normaliser;
+                                when ratio > sigma_thr or < 1/sigma_thr, sigma_s is multiplied
+                                by ratio (kept in [sigma_min, sigma_max]), s~ <- S +
+                                (old/new)(s~ - S) and the K blocks are refactored.  The scaling
+                                reached is kept per instance for warm solves. */
+  int32_t sigma_every;
+  double sigma_thr, sigma_min, sigma_max;
 } nrto_options;
 
 /* Per-instance result of a solve. */
@@ -123,6 +135,9 @@ typedef struct {
   double t_dr_us, t_qp_us, t_kkt_us, t_total_us; /* device wall-clock time of the workgroup in
                                 the DR passes with their K-solves, the (du, p) blocks, the KKT
                                 checks, and the whole solve */
+  double sigma_s;            /* DR scaling at the end of the solve */
+  int32_t sigma_updates;     /* changes of sigma_s during the solve */
+  int32_t pad0;
 } nrto_solve_report;
 
 /* Per-instance result of one successive-linearisation step. */
@@ -137,7 +152,8 @@ typedef struct {
 
 /* Defaults: DR, FP64, 40 ADMM x 100 DR iterations, rho 40, alpha 1,
  * sigma 1, eps_dr 1e-4, eps_kkt 1e-4, r_trust 2 (paper hyperparameter tables);
- * cold_init 0, rho_adapt 0 with rho_mu 10, rho_tau 2, rho_min 1, rho_max 200. */
+ * cold_init 0, rho_adapt 0 with rho_mu 10, rho_tau 2, rho_min 1, rho_max 200,
+ * sigma_adapt 0 with sigma_every 10, sigma_thr 5, sigma_min 1e-4, sigma_max 1e6. */
 void nrto_default_options(nrto_options *opt);
 
 /*

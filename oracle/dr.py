@@ -33,6 +33,20 @@ Two options depart from the printed method (both off by default):
     tau when r_p > mu r_d, rho <- rho / tau when r_d > mu r_p, kept in
     [rho_min, rho_max].  lambda is unscaled, so it is kept as it is; the
     k_v factor does not involve rho, so nothing is refactored.
+  sigma_adapt: balancing of the DR scaling sigma_s (in the spirit of OSQP's
+    step-size rule, Stellato et al., Math. Prog. Comp. 12, 2020): after every
+    sigma_every-th DR iteration of a solve, with S = (p~, eta(K)) the affine
+    point, S_hat its projection, K~ the gain state before the iteration,
+      r_prim = ||S_hat - S||,  r_dual = ||K - K~||,
+      ratio = sqrt((r_prim / max(1, ||S||)) / (r_dual / max(1, ||K||))),
+    sigma_s <- clip(sigma_s ratio, sigma_min, sigma_max) when ratio > sigma_thr
+    or ratio < 1 / sigma_thr; residuals at rounding level (r_prim <=
+    1e-9 max(1, ||S||) or r_dual <= 1e-9 max(1, ||K||)) leave sigma_s as it is.  The cone state keeps its multiplier estimate:
+    s~ <- S + (sigma_old / sigma_new)(s~ - S); the k_v blocks are refactored.
+    With every cone slack, the DR iteration contracts K towards its minimiser
+    by (sigma_chi + sigma_s l)/(q + sigma_chi + sigma_s l) along an eigenvector
+    of sum_j A_hat_j'A_hat_j with eigenvalue l (q: the curvature of Q_v), so a
+    sigma_s fit for the active cones can stall the gains; the rule moves it.
 """
 from __future__ import annotations
 
@@ -67,6 +81,11 @@ class Options:
     rho_tau: float = 2.0
     rho_min: float = 1.0
     rho_max: float = 200.0
+    sigma_adapt: bool = False
+    sigma_every: int = 10
+    sigma_thr: float = 5.0
+    sigma_min: float = 1e-4
+    sigma_max: float = 1e6
 
 
 @dataclasses.dataclass
@@ -81,6 +100,7 @@ class State:
     pt: np.ndarray       # last chi (p~ part)
     pi: np.ndarray
     mu: float
+    sigma_s: Optional[float] = None   # current DR scaling (None: the option's)
 
 
 def zero_state(socp) -> State:
@@ -106,24 +126,34 @@ def cold_state(socp, opt: Options) -> State:
     return st
 
 
+def _sigma(opt: Options, st: State) -> float:
+    return opt.sigma_s if st.sigma_s is None else st.sigma_s
+
+
 def zeta(socp, opt: Options, st: State) -> np.ndarray:
     """Cone multiplier y_eta = sigma_s (eta~ - eta(K)) of the affine-set prox."""
-    return opt.sigma_s * (st.s_t[:, 1:] - eta(socp, st.K))
+    return _sigma(opt, st) * (st.s_t[:, 1:] - eta(socp, st.K))
 
 
 def residual(socp, opt: Options, st: State) -> float:
     return kkt.residual(socp, st.du, st.K, st.p, st.pt, st.pi, st.mu, zeta(socp, opt, st))
 
 
-def factor(socp, opt: Options):
+def factor(socp, opt: Options, sigma_s: Optional[float] = None):
     n = socp.T * socp.nu * socp.nx
-    Hk = Qv_dense(socp) + opt.sigma_chi * np.eye(n) + opt.sigma_s * AtA_dense(socp)
+    ss = opt.sigma_s if sigma_s is None else sigma_s
+    Hk = Qv_dense(socp) + opt.sigma_chi * np.eye(n) + ss * AtA_dense(socp)
     return sla.cho_factor(Hk, lower=True)
 
 
-def dr_steps(socp, opt: Options, st: State, fac, max_steps: int, trace: Optional[Callable] = None):
-    """Run up to max_steps relaxed DR iterations on the current subproblem; returns (steps, r_dr)."""
-    rho, al, sx, ss = opt.rho, opt.alpha, opt.sigma_chi, opt.sigma_s
+def dr_steps(socp, opt: Options, st: State, fac, max_steps: int, trace: Optional[Callable] = None,
+             n_done: int = 0):
+    """Run up to max_steps relaxed DR iterations on the current subproblem.
+    n_done: DR iterations of this solve so far (sigma_adapt acts after every
+    sigma_every-th).  Returns (steps, r_dr, fac) -- fac is refactored when
+    sigma_s changes."""
+    rho, al, sx = opt.rho, opt.alpha, opt.sigma_chi
+    ss = _sigma(opt, st)
     T, nu, nx = socp.T, socp.nu, socp.nx
     r_dr = np.inf
     it = 0
@@ -138,17 +168,33 @@ def dr_steps(socp, opt: Options, st: State, fac, max_steps: int, trace: Optional
         # reflection, cone prox, relaxation
         S_ref = 2.0 * S - st.s_t
         S_hat = project_rows_vec(S_ref)
-        st.K_t = st.K_t + al * (K - st.K_t)
+        dK = K - st.K_t
+        st.K_t = st.K_t + al * dK
         st.pt_t = st.pt_t + al * (pt - st.pt_t)
         dS = al * (S_hat - S)
         st.s_t = st.s_t + dS
         st.K, st.pt = K, pt
         r_dr = float(np.sqrt(np.sum(dS * dS)))
+        if opt.sigma_adapt and (n_done + it) % opt.sigma_every == 0:
+            n_s = max(1.0, float(np.sqrt(np.sum(S * S))))
+            n_k = max(1.0, float(np.sqrt(np.sum(K * K))))
+            r_prim = r_dr / al
+            r_dual = float(np.sqrt(np.sum(dK * dK)))
+            if r_prim > 1e-9 * n_s and r_dual > 1e-9 * n_k:
+                ratio = np.sqrt((r_prim / n_s) / (r_dual / n_k))
+                if ratio > opt.sigma_thr or ratio < 1.0 / opt.sigma_thr:
+                    new = min(max(ss * ratio, opt.sigma_min), opt.sigma_max)
+                    if new != ss:
+                        st.sigma_updates = getattr(st, "sigma_updates", 0) + 1
+                        st.s_t = S + (ss / new) * (st.s_t - S)
+                        ss = new
+                        st.sigma_s = ss
+                        fac = factor(socp, opt, ss)
         if trace is not None:
             trace("dr", it, st)
         if r_dr <= opt.eps_dr_abs + opt.eps_dr_rel * max(1.0, float(np.sqrt(np.sum(st.s_t * st.s_t)))):
             break
-    return it, r_dr
+    return it, r_dr, fac
 
 
 def solve(socp, opt: Options = Options(), st: Optional[State] = None, trace: Optional[Callable] = None):
@@ -156,11 +202,13 @@ def solve(socp, opt: Options = Options(), st: Optional[State] = None, trace: Opt
     opt = dataclasses.replace(opt)      # rho_adapt changes opt.rho
     if st is None:
         st = cold_state(socp, opt)
-    fac = factor(socp, opt)
+    if st.sigma_s is None:
+        st.sigma_s = opt.sigma_s
+    fac = factor(socp, opt, st.sigma_s)
     info = {"admm_iters": 0, "dr_iters": 0, "kkt": np.inf, "status": "maxiter", "r_p": np.inf, "r_d": np.inf}
     pt_prev = st.pt.copy()
     for l in range(1, opt.max_admm + 1):
-        n_dr, _ = dr_steps(socp, opt, st, fac, opt.max_dr, trace)
+        n_dr, _, fac = dr_steps(socp, opt, st, fac, opt.max_dr, trace, info["dr_iters"])
         info["dr_iters"] += n_dr
         c = st.pt - st.lam / opt.rho
         st.du, st.p, st.pi, st.mu = qp.solve(socp.H, socp.h, socp.bmat, socp.g0, c, opt.rho,
@@ -188,4 +236,6 @@ def solve(socp, opt: Options = Options(), st: Optional[State] = None, trace: Opt
                 opt.rho = max(opt.rho_min, opt.rho / opt.rho_tau)
     info["kkt"] = residual(socp, opt, st)
     info["rho"] = opt.rho
+    info["sigma_s"] = st.sigma_s
+    info["sigma_updates"] = getattr(st, "sigma_updates", 0)
     return st, info

@@ -119,6 +119,11 @@ extern "C" void nrto_default_options(nrto_options* o) {
   o->rho_tau = 2.0;
   o->rho_min = 1.0;
   o->rho_max = 200.0;
+  o->sigma_adapt = 0;
+  o->sigma_every = 10;
+  o->sigma_thr = 5.0;
+  o->sigma_min = 1e-4;
+  o->sigma_max = 1e6;
 }
 
 extern "C" const char* nrto_last_error(nrto_ctx c) { return c ? c->err.c_str() : g_err.c_str(); }
@@ -284,6 +289,11 @@ static void fill_opts(const nrto_ctx c, SolveOpts& o, int warm) {
   o.rho_tau = c->opt.rho_tau;
   o.rho_min = c->opt.rho_min;
   o.rho_max = c->opt.rho_max;
+  o.sigma_adapt = c->opt.sigma_adapt;
+  o.sigma_every = c->opt.sigma_every;
+  o.sigma_thr = c->opt.sigma_thr;
+  o.sigma_min = c->opt.sigma_min;
+  o.sigma_max = c->opt.sigma_max;
 }
 
 static nrto_status check_options(nrto_ctx c, const nrto_options* o) {
@@ -301,6 +311,11 @@ static nrto_status check_options(nrto_ctx c, const nrto_options* o) {
   if (o->rho_adapt &&
       !(o->rho_mu > 1 && o->rho_tau > 1 && o->rho_min > 0 && o->rho_min <= o->rho && o->rho <= o->rho_max))
     return ctx_err(c, NRTO_ERR_ARG, "rho_adapt needs rho_mu > 1, rho_tau > 1, 0 < rho_min <= rho <= rho_max");
+  if (o->sigma_adapt != 0 && o->sigma_adapt != 1) return ctx_err(c, NRTO_ERR_ARG, "sigma_adapt must be 0 or 1");
+  if (o->sigma_adapt && !(o->sigma_every >= 1 && o->sigma_thr > 1 && o->sigma_min > 0 &&
+                          o->sigma_min <= o->sigma_s && o->sigma_s <= o->sigma_max))
+    return ctx_err(c, NRTO_ERR_ARG,
+                   "sigma_adapt needs sigma_every >= 1, sigma_thr > 1, 0 < sigma_min <= sigma_s <= sigma_max");
   return NRTO_OK;
 }
 

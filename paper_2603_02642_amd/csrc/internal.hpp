@@ -99,12 +99,14 @@ struct WaveTask {
   int32_t len;     // entries
 };
 
-enum { ISCR_PSI = 0, ISCR_KKT, ISCR_RP, ISCR_RD, ISCR_MUHINT, ISCR_N = 8 };
+enum { ISCR_PSI = 0, ISCR_KKT, ISCR_RP, ISCR_RD, ISCR_MUHINT, ISCR_SIGMA, ISCR_N = 8 };
 
 struct SolveOpts {
   int32_t method, precision, max_admm, max_inner, check_every, warm, cold_init, rho_adapt;
   double rho, alpha, sigma_chi, sigma_s, eps_dr_abs, eps_dr_rel, eps_kkt;
   double rho_mu, rho_tau, rho_min, rho_max;
+  int32_t sigma_adapt, sigma_every;
+  double sigma_thr, sigma_min, sigma_max;
 };
 
 // Device pointers the kernels use.

@@ -82,18 +82,19 @@ __device__ Smem<F> carve(char* base, int T, int nx, int nu, int W) {
 // Block-wide sum of up to 4 values per thread (deterministic order).
 template <int NV>
 __device__ void block_sum(double* red, double (&v)[NV], int W) {
+  static_assert(NV >= 1 && NV <= 8, "up to 8 values (8 waves x 8 slots of the 64 reduction slots)");
 #pragma unroll
   for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
   __syncthreads();
   if (lane_id() == 0) {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) red[wave_id() * 4 + i] = v[i];
+    for (int i = 0; i < NV; ++i) red[wave_id() * NV + i] = v[i];
   }
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     double s = 0.0;
-    for (int w = 0; w < W; ++w) s += red[w * 4 + i];
+    for (int w = 0; w < W; ++w) s += red[w * NV + i];
     v[i] = s;
   }
   __syncthreads();
@@ -285,13 +286,14 @@ __device__ void factor_blocks(const Inst<NX, NU, F>& I, Smem<F>& S, double coef,
 // K-solve.  DR: K = G^-1 (sigma_chi K~ + sigma_s r Racc), K~ += alpha (K - K~).
 // FullADMM: K = G'^-1 (2 RK2 K + rho r Racc).  Racc is zeroed; Kf mirrors K.
 template <int NX, int NU, typename F, int METHOD>
-__device__ void k_solve(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o) {
+__device__ void k_solve(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o, double sig,
+                        double (&kacc)[2]) {
   const int T = I.T;
   for (int col = threadIdx.x; col < T * NX; col += blockDim.x) {
     const int k = col / NX, x = col - k * NX;
     double z[NU];
     if (METHOD == NRTO_DR) {
-      const double a = o.sigma_s * I.r;
+      const double a = sig * I.r;
 #pragma unroll
       for (int u = 0; u < NU; ++u)
         z[u] = o.sigma_chi * I.Kt[(k * NU + u) * NX + x] + a * (double)S.Racc[(u * T + k) * NX + x];
@@ -317,6 +319,8 @@ __device__ void k_solve(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o
       if (METHOD == NRTO_DR) {
         double kt = I.Kt[(k * NU + u) * NX + x];
         I.Kt[(k * NU + u) * NX + x] = kt + o.alpha * (z[u] - kt);
+        kacc[0] += (z[u] - kt) * (z[u] - kt);
+        kacc[1] += z[u] * z[u];
       }
     }
   }
@@ -396,12 +400,13 @@ __device__ __forceinline__ void soc_case(double t, double a, double& that, doubl
 // DR pass: one relaxed DR iteration over all cones of the instance (after the
 // K-solve).  Accumulates sum ||delta s~||^2 and ||s~||^2.
 template <int NX, int NU, typename F>
-__device__ void dr_pass(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o, double rho, double (&acc)[2]) {
+__device__ void dr_pass(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o, double rho, double sig,
+                        double (&acc)[5]) {
   const int T = I.T;
   const int lane = lane_id();
   const F r = (F)I.r;
   const double al = o.alpha;
-  const double den = rho + o.sigma_chi + o.sigma_s;
+  const double den = rho + o.sigma_chi + sig;
   double* ws = S.wscr + wave_id() * 128;
   for (int t = next_task(S.ctr); t < I.ntask; t = next_task(S.ctr)) {
     const WaveTask tk = I.tasks[t];
@@ -417,7 +422,7 @@ __device__ void dr_pass(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o
         const F stv = I.st[e];
         if (le == 0) {
           ptc = (o.sigma_chi * I.C(CA_PTT, c) + rho * I.C(CA_P, c) + I.C(CA_LAM, c) +
-                 o.sigma_s * (double)stv) / den;
+                 sig * (double)stv) / den;
           tr0 = (double)((F)2 * (F)ptc - stv);
         } else {
           int k, x, b;
@@ -431,7 +436,7 @@ __device__ void dr_pass(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o
       const double tref = __shfl(tr0, 0, NRTO_WAVE);
       double that, scale;
       soc_case(tref, a, that, scale);
-      double dsum = 0.0, nsum = 0.0;
+      double dsum = 0.0, nsum = 0.0, ssum = 0.0;
       for (int le = lane; le < tk.len; le += NRTO_WAVE) {
         const int64_t e = tk.ebeg + le;
         const F stv = I.st[e];
@@ -453,6 +458,7 @@ __device__ void dr_pass(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o
         const double dd = al * (double)diff;
         dsum += dd * dd;
         nsum += (double)stn * (double)stn;
+        ssum += (double)s * (double)s;
         if (le == 0) {
           I.C(CA_PT, c) = ptc;
           const double pt0 = I.C(CA_PTT, c);
@@ -463,6 +469,7 @@ __device__ void dr_pass(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o
       }
       acc[0] += dsum;
       acc[1] += nsum;
+      acc[4] += ssum;
     } else {
       // packed short cones: one entry per lane
       const uint64_t mask = I.tmask[t];
@@ -484,7 +491,7 @@ __device__ void dr_pass(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o
         stv = I.st[e];
         if (le == 0) {
           ptc = (o.sigma_chi * I.C(CA_PTT, c) + rho * I.C(CA_P, c) + I.C(CA_LAM, c) +
-                 o.sigma_s * (double)stv) / den;
+                 sig * (double)stv) / den;
           s = (F)ptc;
           ws[64 + cl] = (double)((F)2 * s - stv);
         } else {
@@ -510,6 +517,7 @@ __device__ void dr_pass(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o
         const double dd = al * (double)diff;
         acc[0] += dd * dd;
         acc[1] += (double)stn * (double)stn;
+        acc[4] += (double)s * (double)s;
         if (le == 0) {
           I.C(CA_PT, c) = ptc;
           const double pt0 = I.C(CA_PTT, c);
@@ -1242,7 +1250,8 @@ __device__ int qp_block(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double r
 // FP64 KKT residual (see the oracle's definition).  Uses K (double), the
 // multipliers CA_PI, mu, and zeta from the method state.
 template <int NX, int NU, typename F, int METHOD>
-__device__ double kkt_residual(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o, bool pending, int W) {
+__device__ double kkt_residual(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o, double sig, bool pending,
+                               int W) {
   const int T = I.T;
   const double r = I.r;
   // zero accumulator of sum_j A_hat_j' zeta_j
@@ -1270,7 +1279,7 @@ __device__ double kkt_residual(const Inst<NX, NU, F>& I, Smem<F>& S, const Solve
         const double eta = r * f + (double)I.bhat[e];
         double z;
         if (METHOD == NRTO_DR) {
-          z = o.sigma_s * ((double)I.st[e] - eta);
+          z = sig * ((double)I.st[e] - eta);
         } else {
           double lv = (double)I.st[e];
           if (pending) lv += eta - (double)I.nuv[e];
@@ -1459,6 +1468,42 @@ __device__ void zero_state(const Inst<NX, NU, F>& I) {
   __syncthreads();
 }
 
+// Change of the DR scaling sigma_s -> sigma_s / f keeping the cone multiplier
+// estimate: s~ <- S + f (s~ - S) with S = (p~, eta(K)) of the last DR iteration,
+// and the adjoint accumulator rebuilt from the new s~.
+template <int NX, int NU, typename F>
+__device__ void rescale_pass(const Inst<NX, NU, F>& I, Smem<F>& S, double f) {
+  const int T = I.T;
+  const F r = (F)I.r;
+  for (int i = threadIdx.x; i < NU * T * NX; i += blockDim.x) S.Racc[i] = (F)0;
+  if (threadIdx.x == 0) *S.ctr = 0;
+  __syncthreads();
+  for (int t = next_task(S.ctr); t < I.ntask; t = next_task(S.ctr)) {
+    const WaveTask tk = I.tasks[t];
+    for (int c = tk.cone; c < tk.cone + tk.ncone; ++c) {
+      const int32_t* m = I.cm + c * CM_N;
+      const int e0 = m[CM_EOFF];
+      const int len = 1 + m[CM_NBLK] * NX;
+      for (int le = lane_id(); le < len; le += NRTO_WAVE) {
+        const int64_t e = e0 + le;
+        if (le == 0) {
+          const double sv = I.C(CA_PT, c);
+          I.st[e] = (F)(sv + f * ((double)I.st[e] - sv));
+        } else {
+          int k, x, b;
+          entry_block<NX>(m, le, k, x, b);
+          const F bh = I.bhat[e];
+          const F sv = r * fwd_gemm<NX, NU, F>(I, S, T, k, x, I.bvec + (int64_t)b * NU) + bh;
+          const F sn = (F)((double)sv + f * ((double)I.st[e] - (double)sv));
+          I.st[e] = sn;
+          adj_gemm<NX, NU, F>(S, T, k, x, I.bvec + (int64_t)b * NU, sn - bh);
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // Open-loop cold point (DR): every cone at its value for k_v = 0,
 // s~_j = (||b_hat_j||, b_hat_j) and p = p~ = p~~ = ||b_hat_j||.
 template <int NX, int NU, typename F>
@@ -1516,10 +1561,15 @@ __device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, cha
   for (int c = threadIdx.x; c < I.ng; c += blockDim.x) I.C(CA_PTP, c) = I.C(CA_PT, c);
   __syncthreads();
   bool pending = I.flags[0] != 0;
+  // current DR scaling: the option's value at a cold start, else the one the last
+  // solve of this instance ended with (kept in its report)
+  double sig = o.warm ? g.rep[ii].sigma_s : o.sigma_s;
+  if (!(sig > 0.0)) sig = o.sigma_s;
+  __syncthreads();
 
   // a1: factor the reduced KKT blocks once
   if (METHOD == NRTO_DR)
-    factor_blocks<NX, NU, F>(I, S, o.sigma_s * I.r * I.r, o.sigma_chi);
+    factor_blocks<NX, NU, F>(I, S, sig * I.r * I.r, o.sigma_chi);
   else
     factor_blocks<NX, NU, F>(I, S, rho * I.r * I.r, 0.0);
 
@@ -1531,7 +1581,7 @@ __device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, cha
     __syncthreads();
   }
 
-  int admm = 0, inner = 0, qpn = 0, status = NRTO_MAXITER;
+  int admm = 0, inner = 0, qpn = 0, status = NRTO_MAXITER, sig_updates = 0;
   double kkt = 1e300, rp = 0.0, rd = 0.0;
   for (int l = 1; l <= o.max_admm; ++l) {
     admm = l;
@@ -1539,14 +1589,38 @@ __device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, cha
     if (METHOD == NRTO_DR) {
       // (6a) DR iterations on the {k_v, p~} block, warm-started
       for (int i = 0; i < o.max_inner; ++i) {
-        k_solve<NX, NU, F, NRTO_DR>(I, S, o);
+        double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        {
+          double kacc[2] = {0.0, 0.0};
+          k_solve<NX, NU, F, NRTO_DR>(I, S, o, sig, kacc);
+          acc[2] = kacc[0];
+          acc[3] = kacc[1];
+        }
         if (threadIdx.x == 0) *S.ctr = 0;
         __syncthreads();
-        double acc[2] = {0.0, 0.0};
-        dr_pass<NX, NU, F>(I, S, o, rho, acc);
-        block_sum<2>(S.red, acc, W);
+        dr_pass<NX, NU, F>(I, S, o, rho, sig, acc);
+        block_sum<5>(S.red, acc, W);
         ++inner;
         const double rdr = sqrt(acc[0]);
+        if (o.sigma_adapt && inner % o.sigma_every == 0) {
+          // balance of the DR scaling (block-uniform: acc comes from block sums)
+          const double n_s = fmax(1.0, sqrt(acc[4]));
+          const double n_k = fmax(1.0, sqrt(acc[3]));
+          const double r_prim = rdr / o.alpha;
+          const double r_dual = sqrt(acc[2]);
+          if (r_prim > 1e-9 * n_s && r_dual > 1e-9 * n_k) {
+            const double ratio = sqrt((r_prim / n_s) / (r_dual / n_k));
+            if (ratio > o.sigma_thr || ratio < 1.0 / o.sigma_thr) {
+              const double nsig = fmin(fmax(sig * ratio, o.sigma_min), o.sigma_max);
+              if (nsig != sig) {
+                rescale_pass<NX, NU, F>(I, S, sig / nsig);
+                sig = nsig;
+                ++sig_updates;
+                factor_blocks<NX, NU, F>(I, S, sig * I.r * I.r, o.sigma_chi);
+              }
+            }
+          }
+        }
         if (rdr <= o.eps_dr_abs + o.eps_dr_rel * fmax(1.0, sqrt(acc[1]))) break;
       }
       // p~ of the last chi is in CA_PT, k_v of the last chi in K
@@ -1604,12 +1678,15 @@ __device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, cha
       }
       acc2[0] += (p - pt) * (p - pt);
     }
-    if (METHOD == NRTO_FULLADMM) k_solve<NX, NU, F, NRTO_FULLADMM>(I, S, o);
+    if (METHOD == NRTO_FULLADMM) {
+      double kacc[2] = {0.0, 0.0};
+      k_solve<NX, NU, F, NRTO_FULLADMM>(I, S, o, sig, kacc);
+    }
     block_sum<2>(S.red, acc2, W);
     rp = sqrt(acc2[0]);
     if (METHOD == NRTO_DR) rd = rho * sqrt(acc2[1]);
     if (o.eps_kkt > 0.0 && (l % o.check_every == 0 || l == o.max_admm)) {
-      kkt = kkt_residual<NX, NU, F, METHOD>(I, S, o, pending, W);
+      kkt = kkt_residual<NX, NU, F, METHOD>(I, S, o, sig, pending, W);
       t_kkt += wall_clock64() - t_mark;
       if (kkt <= o.eps_kkt) {
         status = NRTO_OK;
@@ -1629,7 +1706,7 @@ __device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, cha
     pending = false;
     __syncthreads();
   }
-  if (!(o.eps_kkt > 0.0)) kkt = kkt_residual<NX, NU, F, METHOD>(I, S, o, false, W);
+  if (!(o.eps_kkt > 0.0)) kkt = kkt_residual<NX, NU, F, METHOD>(I, S, o, sig, false, W);
   if (threadIdx.x == 0) {
     I.flags[0] = pending ? 1 : 0;
     nrto_solve_report rep;
@@ -1642,6 +1719,8 @@ __device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, cha
     rep.r_d = rd;
     rep.mu = *I.mu;
     rep.rho = rho;
+    rep.sigma_s = sig;
+    rep.sigma_updates = sig_updates;
     // ticks here; the host scales them to microseconds
     rep.t_dr_us = (double)t_dr;
     rep.t_qp_us = (double)t_qp;
@@ -1709,7 +1788,7 @@ warm_kernel(DevPtrs g, SolveOpts o, const int32_t* order, int n, const float* pr
   cold_state<NX, NU, F, NRTO_DR>(I, S, o);
   if (test) {
     load_kf<NX, NU, F>(I, S);
-    r_cold = kkt_residual<NX, NU, F, NRTO_DR>(I, S, o, false, W);
+    r_cold = kkt_residual<NX, NU, F, NRTO_DR>(I, S, o, o.sigma_s, false, W);
   }
   // prediction row of this instance: du (T*NU), K (T*NU*NX as K[k][u][x]), p~ (ng), pi (ng)
   const float* pr = pred + (int64_t)ii * ld;
@@ -1741,13 +1820,14 @@ warm_kernel(DevPtrs g, SolveOpts o, const int32_t* order, int n, const float* pr
   warm_pass<NX, NU, F>(I, S, o);
   __syncthreads();
   double r_warm = 0.0;
-  if (test) r_warm = kkt_residual<NX, NU, F, NRTO_DR>(I, S, o, false, W);
+  if (test) r_warm = kkt_residual<NX, NU, F, NRTO_DR>(I, S, o, o.sigma_s, false, W);
   const bool keep = !test || r_warm <= r_cold;
   if (!keep) cold_state<NX, NU, F, NRTO_DR>(I, S, o);
   if (threadIdx.x == 0) {
     accepted[ii] = keep ? 1 : 0;
     res[2 * ii] = r_warm;
     res[2 * ii + 1] = r_cold;
+    g.rep[ii].sigma_s = o.sigma_s;   // the warm (or cold) point is built for the option's scaling
   }
 }
 

@@ -38,7 +38,9 @@ class Options(C.Structure):
                 ("sigma_s", C.c_double), ("eps_dr_abs", C.c_double), ("eps_dr_rel", C.c_double),
                 ("eps_kkt", C.c_double), ("r_trust", C.c_double), ("cold_init", C.c_int32),
                 ("rho_adapt", C.c_int32), ("rho_mu", C.c_double), ("rho_tau", C.c_double),
-                ("rho_min", C.c_double), ("rho_max", C.c_double)]
+                ("rho_min", C.c_double), ("rho_max", C.c_double), ("sigma_adapt", C.c_int32),
+                ("sigma_every", C.c_int32), ("sigma_thr", C.c_double), ("sigma_min", C.c_double),
+                ("sigma_max", C.c_double)]
 
 
 class SolveReport(C.Structure):
@@ -46,7 +48,8 @@ class SolveReport(C.Structure):
                 ("qp_newton", C.c_int32), ("kkt", C.c_double), ("r_p", C.c_double),
                 ("r_d", C.c_double), ("mu", C.c_double), ("rho", C.c_double),
                 ("t_dr_us", C.c_double), ("t_qp_us", C.c_double), ("t_kkt_us", C.c_double),
-                ("t_total_us", C.c_double)]
+                ("t_total_us", C.c_double), ("sigma_s", C.c_double), ("sigma_updates", C.c_int32),
+                ("pad0", C.c_int32)]
 
 
 class StepReport(C.Structure):

@@ -39,18 +39,23 @@ def _ctx(prob, s, **opt):
 
 @pytest.mark.parametrize("T,L,M,alpha,extra", [(8, 3, 15, 1.0, {}), (8, 2, 10, 1.6, {}), (6, 2, 10, 0.5, {}),
                                                (8, 8, 10, 1.0, {"cold_init": 1, "rho_adapt": 1}),
-                                               (7, 6, 12, 1.2, {"rho_adapt": 1, "rho": 200.0, "sigma_s": 10.0})])
+                                               (7, 6, 12, 1.2, {"rho_adapt": 1, "rho": 200.0, "sigma_s": 10.0}),
+                                               (8, 6, 10, 1.0, {"cold_init": 1, "rho": 200.0, "sigma_s": 100.0,
+                                                                "sigma_adapt": 1, "sigma_every": 3,
+                                                                "sigma_thr": 1.2})])
 def test_dr_iterates_match_oracle_fp64(T, L, M, alpha, extra):
     _torch()
     prob = near_obstacle_problem(T)
     s = linearize.assemble(prob, prob.u_init, 5.0)
     ox = dict(rho=extra.get("rho", 40.0), sigma_s=extra.get("sigma_s", 1.0))
+    sx = dict(sigma_every=extra.get("sigma_every", 10), sigma_thr=extra.get("sigma_thr", 5.0))
     o = dr.Options(max_admm=L, max_dr=M, eps_kkt=0.0, eps_dr_abs=0.0, eps_dr_rel=0.0, alpha=alpha,
                    cold_init="margin" if extra.get("cold_init") else "zero",
-                   rho_adapt=bool(extra.get("rho_adapt")), **ox)
+                   rho_adapt=bool(extra.get("rho_adapt")), sigma_adapt=bool(extra.get("sigma_adapt")), **sx, **ox)
     st, info = dr.solve(s, o)
     c = _ctx(prob, s, method=0, max_admm=L, max_inner=M, eps_kkt=0.0, eps_dr_abs=0.0, eps_dr_rel=0.0,
-             alpha=alpha, r_trust=5.0, cold_init=extra.get("cold_init", 0), rho_adapt=extra.get("rho_adapt", 0), **ox)
+             alpha=alpha, r_trust=5.0, cold_init=extra.get("cold_init", 0), rho_adapt=extra.get("rho_adapt", 0),
+             sigma_adapt=extra.get("sigma_adapt", 0), **sx, **ox)
     rep = c.solve()
     g = c.solution(0)
     gs = c.state(0)
@@ -58,6 +63,10 @@ def test_dr_iterates_match_oracle_fp64(T, L, M, alpha, extra):
     assert rep[0].rho == info["rho"]
     if extra.get("rho_adapt"):
         assert info["rho"] != ox["rho"]        # the balancing acted within L iterations
+    print("sigma", rep[0].sigma_s, info["sigma_s"], "updates", rep[0].sigma_updates, info.get("sigma_updates"), flush=True)
+    assert abs(rep[0].sigma_s - info["sigma_s"]) <= 1e-9 * info["sigma_s"]
+    if extra.get("sigma_adapt"):
+        assert info["sigma_s"] != ox["sigma_s"]
     assert rel_err(g["du"], st.du) <= 1e-9
     assert rel_err(g["K"], st.K) <= 1e-9
     assert rel_err(g["p"], st.p) <= 1e-9
@@ -94,6 +103,30 @@ def test_fulladmm_iterates_match_oracle_fp64(T, L):
     assert rel_err(expand_entries(s, gs["nu"])[:, 1:], st.nu_) <= 1e-9
     ref_kkt = fulladmm.residual(s, o, st)
     assert abs(rep[0].kkt - ref_kkt) <= 1e-9 * max(1.0, ref_kkt)
+
+
+def test_dr_long_cones_with_sigma_balancing_match_oracle():
+    """Quadrotor (cones up to 253 entries: one wave per cone, two passes) with the
+    DR scaling balanced every third iteration."""
+    _torch()
+    prob = synth.config2()
+    prob.T = 20
+    prob.u_init = prob.u_init[:20]
+    s = linearize.assemble(prob, prob.u_init, 2.0)
+    kw = dict(rho=200.0, sigma_s=100.0, sigma_every=3, sigma_thr=1.2)
+    o = dr.Options(max_admm=3, max_dr=8, eps_kkt=0.0, eps_dr_abs=0.0, eps_dr_rel=0.0, sigma_adapt=True, **kw)
+    st, info = dr.solve(s, o)
+    assert info["sigma_s"] != 100.0
+    c = _ctx(prob, s, method=0, max_admm=3, max_inner=8, eps_kkt=0.0, eps_dr_abs=0.0, eps_dr_rel=0.0,
+             r_trust=2.0, sigma_adapt=1, **kw)
+    rep = c.solve()
+    g = c.solution(0)
+    gs = c.state(0)
+    assert abs(rep[0].sigma_s - info["sigma_s"]) <= 1e-9 * info["sigma_s"]
+    assert rel_err(g["du"], st.du) <= 1e-9
+    assert rel_err(g["K"], st.K) <= 1e-9
+    assert rel_err(expand_entries(s, gs["st"]), st.s_t) <= 1e-9
+    assert rel_err(gs["kt"], st.K_t) <= 1e-9
 
 
 def test_trust_region_active_matches_oracle():

@@ -224,3 +224,35 @@ def test_residual_balancing_keeps_the_solution_and_bounds():
     # the penalty only moves by the factor tau inside [rho_min, rho_max]
     lg = np.log2(i1["rho"] / 200.0)
     assert abs(lg - round(lg)) < 1e-12
+
+
+def test_sigma_balancing_keeps_the_solution():
+    s = near_obstacle_socp(T=5)
+    o = dict(rho=200.0, sigma_s=10.0, max_dr=1000, max_admm=400, eps_kkt=1e-7, eps_dr_abs=1e-9, eps_dr_rel=1e-9)
+    s0, i0 = dr.solve(s, dr.Options(**o))
+    s1, i1 = dr.solve(s, dr.Options(sigma_adapt=True, sigma_every=5, sigma_thr=1.5, **o))
+    assert i0["kkt"] <= 1e-7 and i1["kkt"] <= 1e-7
+    assert i1["sigma_s"] != 10.0
+    assert np.allclose(s0.du, s1.du, atol=2e-5) and np.allclose(s0.K, s1.K, atol=2e-5)
+    # the returned multipliers are consistent with the final scaling
+    z = dr.zeta(s, dr.Options(**o), s1)
+    assert np.allclose(z, s1.sigma_s * (s1.s_t[:, 1:] - eta(s, s1.K)))
+
+
+def test_sigma_rescale_keeps_a_fixed_point():
+    # at a DR fixed point S = S_hat, so the rescale s~ <- S + f (s~ - S) with the
+    # refactored scaling leaves (K, p~) fixed: one more DR step moves nothing
+    s = near_obstacle_socp(T=5)
+    o = dr.Options(rho=200.0, sigma_s=10.0, eps_dr_abs=1e-13, eps_dr_rel=1e-13, cold_init="margin")
+    st = dr.cold_state(s, o)
+    st.p[:] = 0.3
+    st.lam[:] = 1.0
+    n, r_dr, _ = dr.dr_steps(s, o, st, dr.factor(s, o), 6000)
+    assert r_dr <= 1e-11
+    S = np.concatenate([st.pt[:, None], eta(s, st.K)], axis=1)
+    f = 0.25
+    st.s_t = S + f * (st.s_t - S)
+    st.sigma_s = o.sigma_s / f
+    K0, pt0 = st.K.copy(), st.pt.copy()
+    dr.dr_steps(s, o, st, dr.factor(s, o, st.sigma_s), 1)
+    assert np.max(np.abs(st.K - K0)) <= 1e-8 and np.max(np.abs(st.pt - pt0)) <= 1e-8
