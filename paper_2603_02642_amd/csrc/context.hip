@@ -89,7 +89,8 @@ template <typename T>
 static nrto_status dalloc(nrto_ctx c, T** p, int64_t n) {
   size_t bytes = (size_t)std::max<int64_t>(n, 1) * sizeof(T);
   void* q = nullptr;
-  if (hipMalloc(&q, bytes) != hipSuccess) return ctx_err(c, NRTO_ERR_ALLOC, "hipMalloc failed");
+  if (hipMalloc(&q, bytes) != hipSuccess)
+    return ctx_err(c, NRTO_ERR_ALLOC, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
   c->allocs.push_back(q);
   if (hipMemsetAsync(q, 0, bytes, c->stream) != hipSuccess) return ctx_err(c, NRTO_ERR_HIP, "hipMemsetAsync failed");
   *p = (T*)q;

@@ -125,6 +125,9 @@ def main():
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
+    import torch
+    torch.cuda.set_device(0)
+    torch.cuda.synchronize()
     X, Y, ok = generate(a.n_train)
     print(f"training on {int(ok.sum())} converged solves", flush=True)
     net, norm = train(X[ok], Y[ok], epochs=a.epochs)
