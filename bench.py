@@ -35,6 +35,24 @@ WORKLOADS = {
 WEIGHTS = os.path.join(ROOT, "paper_2603_02642_amd", "weights", "ws_quadrotor_T50.npz")
 
 HBM_PEAK_GBS = 8000.0
+SOLVER_SRC = os.path.join(ROOT, "paper_2603_02642_amd", "csrc", "solver.hip")
+
+
+def measured_traffic(workload):
+    """HBM bytes per solve launch from the committed FETCH_SIZE / WRITE_SIZE
+    passes of this workload (scaled by the copy calibration recorded with them),
+    or None when no such record exists or the solver source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"solve_kernel_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    with open(SOLVER_SRC, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if rec.get("solver_sha256") != sha:
+        return None
+    return float(rec["bytes_per_launch"])
 
 # NRTO-DR settings of the benchmark: open-loop cold point, rho 200, sigma_s from 100 balanced
 # every 10 DR iterations (threshold 2)
@@ -202,7 +220,8 @@ def main():
                                              max(1, sum(r.admm_iters for rep in phases for r in rep))),
                    "fallback_rate": (float(np.mean(fallback)) if fallback else None)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
+                     "alg_bytes_per_launch": float(alg_bytes.mean()),
                      "kernel": "solve_kernel (NRTO-DR, FP64)", "kernel_ms": float(solve_ms.mean())},
     }
     if not args.no_cpu_baseline:

@@ -1732,11 +1732,12 @@ __device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, cha
 
 // ----------------------------------------------------------------------------
 // Learned warm start for NRTO-DR: set the method state from a prediction
-// (du, K, p~, pi) through the DR fixed-point relations: p = p~, lambda = -pi,
-// chi = (k_v, p~), s = b - A chi, y_j = pi_j (1, -eta_j / ||eta_j||) (zero when
-// eta_j = 0), s~ = s + y / sigma_s, K~ = K, p~~ = p~.  The KKT residual of the
-// warm point is compared with that of the cold (zero) point; the cold point is
-// kept when the warm one is worse.
+// (du, K, p~, pi) through the DR fixed-point relations with the cold point's
+// gains K = K~ = 0: p~ = max(predicted p~_j, ||eta_j||), p = p~~ = p~,
+// lambda = -pi, s = (p~, eta), y_j = pi_j (1, -eta_j / ||eta_j||) (zero when
+// eta_j = 0), s~ = s + y / sigma_s.  The KKT residual of the warm point is
+// compared with that of the cold point; the cold point is kept when the warm one
+// is worse.
 template <int NX, int NU, typename F>
 __device__ void warm_pass(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o) {
   const int T = I.T;
@@ -1757,7 +1758,14 @@ __device__ void warm_pass(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts&
       }
       const double nrm = sqrt(wave_sum(n2));
       const double pi = I.C(CA_PI, c);
-      const double pt = I.C(CA_PT, c);
+      // p~ = max(predicted p~, ||eta_j||): the cone point (p~, eta_j) is feasible
+      const double pt = fmax(I.C(CA_PT, c), nrm);
+      wave_sync();
+      if (lane_id() == 0) {
+        I.C(CA_PT, c) = pt;
+        I.C(CA_PTT, c) = pt;
+        I.C(CA_P, c) = pt;
+      }
       for (int le = lane_id(); le < len; le += NRTO_WAVE) {
         if (le == 0) {
           I.st[e0] = (F)(pt + pi * inv_s);
@@ -1790,23 +1798,22 @@ warm_kernel(DevPtrs g, SolveOpts o, const int32_t* order, int n, const float* pr
     load_kf<NX, NU, F>(I, S);
     r_cold = kkt_residual<NX, NU, F, NRTO_DR>(I, S, o, o.sigma_s, false, W);
   }
-  // prediction row of this instance: du (T*NU), K (T*NU*NX as K[k][u][x]), p~ (ng), pi (ng)
+  // prediction row of this instance: du (T*NU), K (T*NU*NX as K[k][u][x]), p~ (ng), pi (ng).
+  // The gains of the warm point stay those of the cold point (zero): a predicted
+  // K with small errors along directions where every cone is slack would have to
+  // be removed by the DR iteration's slowest mode.
   const float* pr = pred + (int64_t)ii * ld;
   for (int i = threadIdx.x; i < T * NU; i += blockDim.x) I.du[i] = (double)pr[i];
-  pr += T * NU;
-  for (int i = threadIdx.x; i < T * NU * NX; i += blockDim.x) {
-    I.K[i] = (double)pr[i];
-    I.Kt[i] = (double)pr[i];
-  }
-  pr += T * NU * NX;
+  pr += T * NU * (NX + 1);
   for (int c = threadIdx.x; c < I.ng; c += blockDim.x) {
-    const double pt = (double)pr[c];
     const double pi = fmax(0.0, (double)pr[I.ng + c]);
-    I.C(CA_PT, c) = pt;
-    I.C(CA_PTT, c) = pt;
-    I.C(CA_P, c) = pt;
+    I.C(CA_PT, c) = (double)pr[c];   // the predicted p~, made cone-feasible by warm_pass
     I.C(CA_PI, c) = pi;
     I.C(CA_LAM, c) = -pi;
+  }
+  for (int i = threadIdx.x; i < T * NU * NX; i += blockDim.x) {
+    I.K[i] = 0.0;
+    I.Kt[i] = 0.0;
   }
   __syncthreads();
   load_kf<NX, NU, F>(I, S);
