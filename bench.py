@@ -117,6 +117,8 @@ def main():
     ap.add_argument("--max-inner", type=int, default=100)
     ap.add_argument("--check-every", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="launch the solve eagerly instead of replaying "
+                                                             "its captured HIP graph")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -161,12 +163,20 @@ def main():
     bpp = _bytes_per_pass(ctx, 0)
     fallback = []
 
+    use_graph = not args.no_graph and not learned
+    graph = [False]
+
     def solve():
         if learned:
             net.infer(feats, out=pred)
             acc, _ = ctx.warm_start(pred)
             fallback.append(float(1.0 - acc.mean()))
             ctx.solve_async(warm=True)
+        elif use_graph:
+            if not graph[0]:
+                ctx.capture_step(warm=False, with_linearize=False)   # the solve launches only
+                graph[0] = True
+            ctx.launch_step()
         else:
             ctx.solve_async()
 
@@ -225,7 +235,8 @@ def main():
                                          for k in ("t_dr_us", "t_qp_us", "t_kkt_us", "t_total_us")},
                    "riccati_per_admm": float(sum(r.qp_newton for rep in phases for r in rep) /
                                              max(1, sum(r.admm_iters for rep in phases for r in rep))),
-                   "fallback_rate": (float(np.mean(fallback)) if fallback else None)},
+                   "fallback_rate": (float(np.mean(fallback)) if fallback else None),
+                   "solve_launch": "hipGraph replay" if use_graph else "eager"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
                      "alg_bytes_per_launch": float(alg_bytes.mean()),

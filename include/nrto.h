@@ -271,6 +271,19 @@ nrto_status nrto_scp_step(nrto_ctx ctx, nrto_step_report *rep);
  * NULL; its status, kkt and iteration counts are those of the last solve.
  */
 nrto_status nrto_scp_accept(nrto_ctx ctx, nrto_step_report *rep);
+/*
+ * Capture one step -- nrto_linearize (if with_linearize) followed by the solve
+ * launches of nrto_solve_socp(ctx, warm, NULL) -- into a HIP graph kept by the context, and
+ * replay it with nrto_launch_step (asynchronous on the context's stream; read the
+ * results with nrto_get_reports / nrto_get_solution).  For callers that step the
+ * same batch many times without host work in between (no allocation, copy or
+ * synchronisation happens inside the step).  The context's stream must not be
+ * the default stream.  nrto_set_options drops the captured step (its kernels
+ * carry the options of the capture).  NRTO-DR, FP64 only.
+ */
+nrto_status nrto_capture_step(nrto_ctx ctx, int32_t warm, int32_t with_linearize);
+nrto_status nrto_launch_step(nrto_ctx ctx);
+
 /* Per-instance reports of the last solve (n_inst entries, host memory), e.g. after
  * nrto_solve_socp with rep = NULL.  Synchronises the context's stream. */
 nrto_status nrto_get_reports(nrto_ctx ctx, nrto_solve_report *rep);

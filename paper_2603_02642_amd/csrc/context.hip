@@ -61,6 +61,7 @@ struct nrto_ctx_s {
   std::vector<double> rtrust;  // per-instance trust radius (host copy)
   double* scp_out = nullptr;   // 5 per instance: merit-test results of nrto_scp_step
   double us_per_tick = 0.0;    // device wall clock period in microseconds
+  hipGraphExec_t step_exec = nullptr;  // captured linearise + solve (nrto_capture_step)
 };
 
 // Scale the wall-clock tick counts of device-written reports to microseconds.
@@ -337,6 +338,10 @@ extern "C" nrto_status nrto_set_options(nrto_ctx c, const nrto_options* o) {
   if (!c) return set_global_error(NRTO_ERR_ARG, "null context");
   nrto_status s = check_options(c, o);
   if (s != NRTO_OK) return s;
+  if (c->step_exec) {
+    HIPCHK(c, hipGraphExecDestroy(c->step_exec));   // its kernels carry the old options
+    c->step_exec = nullptr;
+  }
   c->opt = *o;
   std::vector<InstDev> d(c->n);
   for (int i = 0; i < c->n; ++i) {
@@ -486,8 +491,9 @@ extern "C" nrto_status nrto_setup(const nrto_problem* probs, int32_t n, const nr
 
 extern "C" void nrto_destroy(nrto_ctx c) {
   if (!c) return;
-  if (c->stream) hipStreamSynchronize(c->stream);
-  else hipDeviceSynchronize();
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
   for (void* p : c->allocs) hipFree(p);
   delete c;
 }
@@ -715,6 +721,55 @@ extern "C" nrto_status nrto_get_nominal(nrto_ctx c, int32_t inst, double* uhat, 
   HIPCHK(c, copy_out(uhat, c->g.uhat + d.oU, (size_t)d.T * d.nu, c->stream));
   HIPCHK(c, copy_out(K, c->g.K + d.oK, (size_t)d.T * d.nu * d.nx, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  return NRTO_OK;
+}
+
+static nrto_status launch_solve(nrto_ctx c, int warm) {
+  SolveOpts o;
+  fill_opts(c, o, warm ? 1 : 0);
+  for (int gi = 0; gi < 3; ++gi) {
+    const int cnt = c->group_off[gi + 1] - c->group_off[gi];
+    HIPCHK(c, launch_solver(c->g, o, c->group_nx[gi], c->order + c->group_off[gi], cnt, c->threads, c->smem,
+                            c->stream));
+  }
+  return NRTO_OK;
+}
+
+extern "C" nrto_status nrto_capture_step(nrto_ctx c, int32_t warm, int32_t with_linearize) {
+  if (!c) return set_global_error(NRTO_ERR_ARG, "null context");
+  if (!c->stream) return ctx_err(c, NRTO_ERR_ARG, "graph capture needs a non-default stream");
+  if (c->opt.method == NRTO_FULLADMM || c->opt.precision == NRTO_FP32)
+    return ctx_err(c, NRTO_ERR_STATE, "the FullADMM and FP32 device paths are switched off");
+  if (c->step_exec) {
+    HIPCHK(c, hipGraphExecDestroy(c->step_exec));
+    c->step_exec = nullptr;
+  }
+  int max_ng = 0;
+  for (auto& h : c->hi) max_ng = std::max(max_ng, h.d.ng);
+  HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = with_linearize ? launch_linearize(c->g, c->n, max_ng, c->stream) : hipSuccess;
+  nrto_status s = (e == hipSuccess) ? launch_solve(c, warm) : NRTO_ERR_HIP;
+  hipGraph_t graph = nullptr;
+  hipError_t e2 = hipStreamEndCapture(c->stream, &graph);
+  if (e != hipSuccess) return ctx_err(c, NRTO_ERR_HIP, std::string("capture: ") + hipGetErrorString(e));
+  if (s != NRTO_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s;
+  }
+  if (e2 != hipSuccess) return ctx_err(c, NRTO_ERR_HIP, std::string("end capture: ") + hipGetErrorString(e2));
+  e = hipGraphInstantiate(&c->step_exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    c->step_exec = nullptr;
+    return ctx_err(c, NRTO_ERR_HIP, std::string("instantiate: ") + hipGetErrorString(e));
+  }
+  return NRTO_OK;
+}
+
+extern "C" nrto_status nrto_launch_step(nrto_ctx c) {
+  if (!c) return set_global_error(NRTO_ERR_ARG, "null context");
+  if (!c->step_exec) return ctx_err(c, NRTO_ERR_STATE, "no captured step (call nrto_capture_step)");
+  HIPCHK(c, hipGraphLaunch(c->step_exec, c->stream));
   return NRTO_OK;
 }
 

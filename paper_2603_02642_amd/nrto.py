@@ -92,6 +92,8 @@ def load() -> C.CDLL:
         "nrto_scp_step": (i32, [vp, P(StepReport)]),
         "nrto_scp_accept": (i32, [vp, P(StepReport)]),
         "nrto_get_reports": (i32, [vp, P(SolveReport)]),
+        "nrto_capture_step": (i32, [vp, i32, i32]),
+        "nrto_launch_step": (i32, [vp]),
         "nrto_get_nominal": (i32, [vp, i32, _dp, _dp]),
         "nrto_warm_start": (i32, [vp, vp, i64, i32, P(C.c_int32), _dp]),
     }
@@ -267,6 +269,13 @@ class Context:
         rep = (StepReport * self.n)()
         _check(load().nrto_scp_step(self.h, rep), self.h)
         return list(rep)
+
+    def capture_step(self, warm: bool = False, with_linearize: bool = True):
+        """Capture (linearise +) solve into a HIP graph (non-default stream only)."""
+        _check(load().nrto_capture_step(self.h, 1 if warm else 0, 1 if with_linearize else 0), self.h)
+
+    def launch_step(self):
+        _check(load().nrto_launch_step(self.h), self.h)
 
     def reports(self) -> List[SolveReport]:
         rep = (SolveReport * self.n)()

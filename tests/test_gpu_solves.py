@@ -220,3 +220,61 @@ def test_robust_satisfaction_of_gpu_policy():
                            robust.edge_samples(12, 300, s, g["du"], g["K"])]):
         dx, dU = robust.linear_rollout(s, g["du"], g["K"], zeta)
         assert np.max(robust.linear_constraints(s, dx, dU)) <= 1e-4
+
+
+def test_full_size_batches_sampled_against_oracle():
+    """The 2048-instance mixed batch in the bench's launch configuration (256
+    threads per instance workgroup): fixed iteration counts, three sampled
+    instances (shortest and longest horizon of each model) checked against the
+    oracle one by one."""
+    _torch()
+    from paper_2603_02642_amd import nrto
+    probs = [synth.config4_instance(i if i < 1024 else 1024 + (i - 1024)) for i in range(2048)]
+    kw = dict(rho=200.0, sigma_s=100.0)
+    o = nrto.default_options(method=0, max_admm=2, max_inner=6, eps_kkt=0.0, eps_dr_abs=0.0, eps_dr_rel=0.0,
+                             cold_init=1, **kw)
+    c = nrto.Context(probs, o)
+    c.linearize()
+    c.solve()
+    Ts = np.array([p.T for p in probs])
+    pick = [int(np.argmin(Ts[:1024])), int(np.argmax(Ts[:1024])), 1024 + int(np.argmax(Ts[1024:]))]
+    for i in pick:
+        p = probs[i]
+        s = linearize.assemble(p, p.u_init, 2.0)
+        st, _ = dr.solve(s, dr.Options(max_admm=2, max_dr=6, eps_kkt=0.0, eps_dr_abs=0.0, eps_dr_rel=0.0,
+                                       cold_init="margin", **kw))
+        g = c.solution(i)
+        assert rel_err(g["du"], st.du) <= 1e-9, (i, p.T)
+        assert rel_err(g["K"], st.K) <= 1e-9, (i, p.T)
+
+
+@pytest.mark.parametrize("case", ["T1_no_obstacles", "zero_radius", "many_obstacles_T2"])
+def test_degenerate_instances_match_oracle(case):
+    _torch()
+    from paper_2603_02642_amd import nrto
+    prob = synth.config1()
+    if case == "T1_no_obstacles":
+        prob.T = 1
+        prob.u_init = prob.u_init[:1]
+        prob.obstacles = np.zeros((0, 3))
+    elif case == "zero_radius":
+        prob.T = 6
+        prob.u_init = np.tile([1.0, 0.0], (6, 1))
+        prob.radius = 0.0
+        prob.obstacles = np.array([[0.45, 0.3, 0.15]])
+    else:
+        prob.T = 2
+        prob.u_init = prob.u_init[:2]
+        prob.obstacles = np.array([[0.2 + 0.1 * k, 0.3, 0.05] for k in range(10)])
+    s = linearize.assemble(prob, prob.u_init, 1.0)
+    o = dr.Options(max_admm=3, max_dr=8, eps_kkt=0.0, eps_dr_abs=0.0, eps_dr_rel=0.0)
+    st, _ = dr.solve(s, o)
+    c = nrto.Context([prob], nrto.default_options(method=0, max_admm=3, max_inner=8, eps_kkt=0.0,
+                                                  eps_dr_abs=0.0, eps_dr_rel=0.0, r_trust=1.0))
+    c.upload_socp(0, **compact_socp(s))
+    c.solve()
+    g = c.solution(0)
+    assert rel_err(g["du"], st.du) <= 1e-9
+    assert rel_err(g["K"], st.K) <= 1e-9
+    if case == "zero_radius":
+        assert np.max(np.abs(g["K"])) == 0.0
