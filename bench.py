@@ -119,6 +119,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch the solve eagerly instead of replaying "
                                                              "its captured HIP graph")
+    ap.add_argument("--no-autotune", action="store_true", help="batched workloads: keep the default "
+                                                                "workgroup size instead of tuning it")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -160,6 +162,11 @@ def main():
             net = L.load_net(WEIGHTS, max_batch=len(probs))
             feats = torch.from_numpy(L.features(probs)).to(dev)
             pred = torch.empty((len(probs), L.WIDTHS[-1]), dtype=torch.float32, device=dev)
+    tuned = None
+    if len(probs) > 1 and not args.no_autotune:
+        from paper_2603_02642_amd import autotune
+        best, times = autotune.tune_block_threads(ctx, stream)
+        tuned = {"block_threads": best, "solve_ms_2x10_iterations": {str(k): round(v, 2) for k, v in times.items()}}
     bpp = _bytes_per_pass(ctx, 0)
     fallback = []
 
@@ -236,7 +243,8 @@ def main():
                    "riccati_per_admm": float(sum(r.qp_newton for rep in phases for r in rep) /
                                              max(1, sum(r.admm_iters for rep in phases for r in rep))),
                    "fallback_rate": (float(np.mean(fallback)) if fallback else None),
-                   "solve_launch": "hipGraph replay" if use_graph else "eager"},
+                   "solve_launch": "hipGraph replay" if use_graph else "eager",
+                   "autotune": tuned},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
                      "alg_bytes_per_launch": float(alg_bytes.mean()),

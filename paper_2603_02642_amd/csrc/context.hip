@@ -342,7 +342,16 @@ extern "C" nrto_status nrto_set_options(nrto_ctx c, const nrto_options* o) {
     HIPCHK(c, hipGraphExecDestroy(c->step_exec));   // its kernels carry the old options
     c->step_exec = nullptr;
   }
+  const nrto_options prev = c->opt;
   c->opt = *o;
+  if (o->block_threads != prev.block_threads || o->precision != prev.precision) {
+    s = configure_launch(c);       // workgroup size and LDS of the launches
+    if (s != NRTO_OK) {
+      c->opt = prev;
+      (void)configure_launch(c);
+      return s;
+    }
+  }
   std::vector<InstDev> d(c->n);
   for (int i = 0; i < c->n; ++i) {
     c->hi[i].d.r_trust = o->r_trust;

@@ -278,3 +278,20 @@ def test_degenerate_instances_match_oracle(case):
     assert rel_err(g["K"], st.K) <= 1e-9
     if case == "zero_radius":
         assert np.max(np.abs(g["K"])) == 0.0
+
+
+def test_autotuner_picks_a_measured_block_size():
+    torch = _torch()
+    from paper_2603_02642_amd import autotune, nrto
+    probs = [synth.config4_instance(i) for i in list(range(16)) + list(range(1024, 1040))]
+    o = nrto.default_options(method=0, cold_init=1, rho=200.0, sigma_s=100.0, max_admm=7)
+    stream = torch.cuda.Stream()
+    c = nrto.Context(probs, o, stream=stream.cuda_stream)
+    best, times = autotune.tune_block_threads(c, stream)
+    assert best in autotune.CANDIDATES and best in times
+    assert times[best] == min(times.values()) and all(t > 0 for t in times.values())
+    # the context keeps its own options, with the tuned workgroup size
+    assert c.options.block_threads == best and c.options.max_admm == 7
+    c.linearize()
+    rep = c.solve()
+    assert all(r.admm_iters <= 7 for r in rep)
