@@ -38,10 +38,11 @@ HBM_PEAK_GBS = 8000.0
 SOLVER_SRC = os.path.join(ROOT, "paper_2603_02642_amd", "csrc", "solver.hip")
 
 
-def measured_traffic(workload):
+def measured_traffic(workload, policy):
     """HBM bytes per solve launch from the committed FETCH_SIZE / WRITE_SIZE
     passes of this workload (scaled by the copy calibration recorded with them),
-    or None when no such record exists or the solver source changed since."""
+    or None when no such record exists, or the solver source or the solver
+    settings changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"solve_kernel_{workload}_traffic.json")
     if not os.path.exists(path):
@@ -50,13 +51,13 @@ def measured_traffic(workload):
         rec = json.load(f)
     with open(SOLVER_SRC, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
-    if rec.get("solver_sha256") != sha:
+    if rec.get("solver_sha256") != sha or rec.get("policy") != policy:
         return None
     return float(rec["bytes_per_launch"])
 
-# NRTO-DR settings of the benchmark: open-loop cold point, rho 200, sigma_s from 100 balanced
+# NRTO-DR settings of the benchmark: open-loop cold point, rho 50, sigma_s from 100 balanced
 # every 10 DR iterations (threshold 2)
-TUNED = dict(rho=200.0, sigma_s=100.0, cold_init=1, sigma_adapt=1, sigma_thr=2.0)
+TUNED = dict(rho=50.0, sigma_s=100.0, cold_init=1, sigma_adapt=1, sigma_thr=2.0)
 
 
 def _problems(name, n=None):
@@ -116,6 +117,10 @@ def main():
     ap.add_argument("--max-admm", type=int, default=200)
     ap.add_argument("--max-inner", type=int, default=100)
     ap.add_argument("--check-every", type=int, default=1)
+    ap.add_argument("--rho", type=float, default=TUNED["rho"])
+    ap.add_argument("--sigma-s", type=float, default=TUNED["sigma_s"])
+    ap.add_argument("--sigma-thr", type=float, default=TUNED["sigma_thr"])
+    ap.add_argument("--sigma-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch the solve eagerly instead of replaying "
                                                              "its captured HIP graph")
@@ -146,9 +151,10 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.Stream()
     probs = _problems(args.workload, args.instances or None)
+    pol = dict(TUNED, rho=args.rho, sigma_s=args.sigma_s, sigma_thr=args.sigma_thr, sigma_every=args.sigma_every)
     opt = nrto.default_options(method=nrto.NRTO_DR, precision=nrto.NRTO_FP64, max_admm=args.max_admm,
                                max_inner=args.max_inner, check_every=args.check_every, eps_kkt=1e-4,
-                               r_trust=2.0, **TUNED)
+                               r_trust=2.0, **pol)
     learned = args.workload == "learned_quadrotor_4096"
     # successive-linearisation steps advance the nominal trajectories; the two
     # quadrotor-4096 workloads re-solve the first SOCP (the one the network is
@@ -237,6 +243,7 @@ def main():
                    "instances": ctx.n, "solves": int(conv.size), "converged": int(conv.sum()),
                    "admm_iters_mean": float(admm.mean()), "dr_iters_mean": float(inner.mean()),
                    "max_admm": args.max_admm, "max_inner": args.max_inner,
+                   "policy": {k: pol[k] for k in ("rho", "sigma_s", "sigma_thr", "sigma_every")},
                    "solve_ms_per_step": float(solve_ms.mean()),
                    "workgroup_us_mean": {k: float(np.mean([getattr(r, k) for rep in phases for r in rep]))
                                          for k in ("t_dr_us", "t_qp_us", "t_kkt_us", "t_total_us")},
@@ -246,7 +253,8 @@ def main():
                    "solve_launch": "hipGraph replay" if use_graph else "eager",
                    "autotune": tuned},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload, {k: pol[k] for k in ("rho", "sigma_s", "sigma_thr",
+                                                                                        "sigma_every")}),
                      "alg_bytes_per_launch": float(alg_bytes.mean()),
                      "kernel": "solve_kernel (NRTO-DR, FP64)", "kernel_ms": float(solve_ms.mean())},
     }

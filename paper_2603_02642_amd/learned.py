@@ -36,7 +36,7 @@ WIDTHS = [64, 256, 256, 256, 256, 3800]
 
 def dr_options(**kw):
     base = dict(method=nrto.NRTO_DR, precision=nrto.NRTO_FP64, max_admm=200, max_inner=100,
-                check_every=1, rho=200.0, sigma_s=100.0, cold_init=1, sigma_adapt=1, sigma_thr=2.0,
+                check_every=1, rho=50.0, sigma_s=100.0, cold_init=1, sigma_adapt=1, sigma_thr=2.0,
                 eps_kkt=1e-4)
     base.update(kw)
     return nrto.default_options(**base)
