@@ -62,6 +62,8 @@ struct nrto_ctx_s {
   double* scp_out = nullptr;   // 5 per instance: merit-test results of nrto_scp_step
   double us_per_tick = 0.0;    // device wall clock period in microseconds
   hipGraphExec_t step_exec = nullptr;  // captured linearise + solve (nrto_capture_step)
+  int32_t* ws_acc = nullptr;   // nrto_warm_start: accepted flag per instance
+  double* ws_res = nullptr;    // nrto_warm_start: (warm, cold) residual per instance
 };
 
 // Scale the wall-clock tick counts of device-written reports to microseconds.
@@ -443,6 +445,8 @@ extern "C" nrto_status nrto_setup(const nrto_problem* probs, int32_t n, const nr
   ALLOC(g.flags, (int64_t)n * 4);
   ALLOC(g.rep, n);
   ALLOC(c->scp_out, 5 * (int64_t)n);
+  ALLOC(c->ws_acc, n);
+  ALLOC(c->ws_res, 2 * (int64_t)n);
   ALLOC(c->order, n);
 #undef ALLOC
   // uploads
@@ -838,13 +842,8 @@ extern "C" nrto_status nrto_warm_start(nrto_ctx c, const float* pred, int64_t ld
   for (auto& h : c->hi)
     if (ld < (int64_t)h.d.T * h.d.nu * (h.d.nx + 1) + 2 * (int64_t)h.d.ng)
       return ctx_err(c, NRTO_ERR_ARG, "prediction row shorter than du + K + p~ + pi");
-  int32_t* acc = nullptr;
-  double* res = nullptr;
-  if (hipMalloc(&acc, sizeof(int32_t) * c->n) != hipSuccess) return ctx_err(c, NRTO_ERR_ALLOC, "hipMalloc failed");
-  if (hipMalloc(&res, sizeof(double) * 2 * c->n) != hipSuccess) {
-    (void)hipFree(acc);
-    return ctx_err(c, NRTO_ERR_ALLOC, "hipMalloc failed");
-  }
+  int32_t* acc = c->ws_acc;
+  double* res = c->ws_res;
   SolveOpts o;
   fill_opts(c, o, 1);
   hipError_t e = hipSuccess;
@@ -856,8 +855,6 @@ extern "C" nrto_status nrto_warm_start(nrto_ctx c, const float* pred, int64_t ld
   if (e == hipSuccess && accepted) e = hipMemcpyAsync(accepted, acc, sizeof(int32_t) * c->n, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess && residuals) e = hipMemcpyAsync(residuals, res, sizeof(double) * 2 * c->n, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  (void)hipFree(acc);
-  (void)hipFree(res);
   if (e != hipSuccess) return ctx_err(c, NRTO_ERR_HIP, hipGetErrorString(e));
   return NRTO_OK;
 }

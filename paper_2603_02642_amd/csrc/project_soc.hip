@@ -117,12 +117,15 @@ extern "C" nrto_status nrto_project_soc(const void* in, void* out, const int64_t
     int* bad = nullptr;
     if (hipMalloc(&bad, sizeof(int)) != hipSuccess) return set_global_error(NRTO_ERR_ALLOC, "hipMalloc failed");
     int zero = 0, h = 0;
-    hipMemcpyAsync(bad, &zero, sizeof(int), hipMemcpyHostToDevice, s);
+    hipError_t e = hipMemcpyAsync(bad, &zero, sizeof(int), hipMemcpyHostToDevice, s);
     int64_t nb = (n_cones + 255) / 256;
-    validate_offsets_kernel<<<dim3((unsigned)nb), dim3(256), 0, s>>>(seg_off, n_cones, n_entries, bad);
-    hipMemcpyAsync(&h, bad, sizeof(int), hipMemcpyDeviceToHost, s);
-    hipError_t e = hipStreamSynchronize(s);
-    hipFree(bad);
+    if (e == hipSuccess) {
+      validate_offsets_kernel<<<dim3((unsigned)nb), dim3(256), 0, s>>>(seg_off, n_cones, n_entries, bad);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, bad, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(bad);
     if (e != hipSuccess) return set_global_error(NRTO_ERR_HIP, hipGetErrorString(e));
     if (h) return set_global_error(NRTO_ERR_ARG, "seg_off must start at 0, be non-decreasing and end at n_entries");
   }
