@@ -163,11 +163,14 @@ def main():
     with torch.cuda.stream(stream):
         ctx = nrto.Context(probs, opt, stream=stream.cuda_stream)
         net = feats = pred = None
+        gains = True
         if learned:
             from paper_2603_02642_amd import learned as L
             net = L.load_net(WEIGHTS, max_batch=len(probs))
+            gains = L.rows_have_gains(WEIGHTS)
             feats = torch.from_numpy(L.features(probs)).to(dev)
-            pred = torch.empty((len(probs), L.WIDTHS[-1]), dtype=torch.float32, device=dev)
+            width = int(np.load(WEIGHTS, allow_pickle=False)["widths"][-1])
+            pred = torch.empty((len(probs), width), dtype=torch.float32, device=dev)
     tuned = None
     if len(probs) > 1 and not args.no_autotune:
         from paper_2603_02642_amd import autotune
@@ -182,7 +185,7 @@ def main():
     def solve():
         if learned:
             net.infer(feats, out=pred)
-            acc, _ = ctx.warm_start(pred)
+            acc, _ = ctx.warm_start(pred, gains=gains)
             fallback.append(float(1.0 - acc.mean()))
             ctx.solve_async(warm=True)
         elif use_graph:

@@ -245,15 +245,19 @@ nrto_status nrto_set_state(nrto_ctx ctx, int32_t inst, const double *st, const d
 /*
  * Learned warm start of NRTO-DR (step a10): set the method state of every
  * instance from a prediction row (device float32; row i at pred + i*ld) laid
- * out as du (T*nu), K (T*nu*nx, K[k][u][x]), p~ (n_g), pi (n_g), through the DR
- * fixed-point relations p = p~, lambda = -pi, s~ = (b - A chi) + y / sigma_s with
- * y_j = pi_j (1, -eta_j / ||eta_j||), K~ = K.  With fallback_test != 0 the FP64
- * KKT residual of the warm point is compared with that of the cold (zero)
- * point and the cold point is kept when the warm one is worse.  accepted
- * (host, n_inst, may be NULL) receives 1 where the warm point was kept;
- * residuals (host, 2*n_inst, may be NULL) the (warm, cold) residuals.  Follow
- * with nrto_solve_socp(ctx, 1, ...).  Requires method NRTO_DR.
+ * out as du (T*nu), K (T*nu*nx, K[k][u][x]), p~ (n_g), pi (n_g) -- or, with the
+ * flag NRTO_WS_NO_GAINS, du, p~, pi only.  The state is rebuilt through the DR
+ * fixed-point relations with the cold point's gains (K = K~ = 0; a predicted K
+ * is not used): p~_j = max(predicted p~_j, ||eta_j||), p = p~~ = p~,
+ * lambda = -pi, s~ = (p~, eta) + y / sigma_s with y_j = pi_j (1, -eta_j/||eta_j||).
+ * fallback_test (flags): bit 0 = compare the FP64 KKT residual of the warm point
+ * with that of the cold point and keep the cold point where the warm one is
+ * worse; NRTO_WS_NO_GAINS (bit 1) = rows without K.  accepted (host, n_inst, may
+ * be NULL) receives 1 where the warm point was kept; residuals (host, 2*n_inst,
+ * may be NULL) the (warm, cold) residuals.  Follow with nrto_solve_socp(ctx, 1,
+ * ...).  Requires method NRTO_DR.
  */
+#define NRTO_WS_NO_GAINS 2
 nrto_status nrto_warm_start(nrto_ctx ctx, const float *pred, int64_t ld, int32_t fallback_test,
                             int32_t *accepted, double *residuals);
 

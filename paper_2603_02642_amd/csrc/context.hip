@@ -839,9 +839,11 @@ extern "C" nrto_status nrto_warm_start(nrto_ctx c, const float* pred, int64_t ld
   if (c->opt.method != NRTO_DR) return ctx_err(c, NRTO_ERR_STATE, "the learned warm start targets NRTO-DR");
   if (c->opt.precision == NRTO_FP32)
     return ctx_err(c, NRTO_ERR_STATE, "the FP32 solver path is switched off; use NRTO_FP64");
+  if (fallback_test & ~3) return ctx_err(c, NRTO_ERR_ARG, "unknown warm-start flags");
+  const bool gains = !(fallback_test & NRTO_WS_NO_GAINS);
   for (auto& h : c->hi)
-    if (ld < (int64_t)h.d.T * h.d.nu * (h.d.nx + 1) + 2 * (int64_t)h.d.ng)
-      return ctx_err(c, NRTO_ERR_ARG, "prediction row shorter than du + K + p~ + pi");
+    if (ld < (int64_t)h.d.T * h.d.nu * (gains ? h.d.nx + 1 : 1) + 2 * (int64_t)h.d.ng)
+      return ctx_err(c, NRTO_ERR_ARG, "prediction row shorter than du (+ K) + p~ + pi");
   int32_t* acc = c->ws_acc;
   double* res = c->ws_res;
   SolveOpts o;
@@ -850,7 +852,7 @@ extern "C" nrto_status nrto_warm_start(nrto_ctx c, const float* pred, int64_t ld
   for (int gi = 0; gi < 3 && e == hipSuccess; ++gi) {
     const int cnt = c->group_off[gi + 1] - c->group_off[gi];
     e = launch_warm(c->g, o, c->group_nx[gi], c->order + c->group_off[gi], cnt, c->threads, c->smem, pred, ld,
-                    fallback_test ? 1 : 0, acc, res, c->stream);
+                    fallback_test & 3, acc, res, c->stream);
   }
   if (e == hipSuccess && accepted) e = hipMemcpyAsync(accepted, acc, sizeof(int32_t) * c->n, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess && residuals) e = hipMemcpyAsync(residuals, res, sizeof(double) * 2 * c->n, hipMemcpyDeviceToHost, c->stream);

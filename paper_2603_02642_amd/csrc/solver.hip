@@ -1794,7 +1794,7 @@ warm_kernel(DevPtrs g, SolveOpts o, const int32_t* order, int n, const float* pr
   const int T = I.T;
   double r_cold = 1e300;
   cold_state<NX, NU, F, NRTO_DR>(I, S, o);
-  if (test) {
+  if (test & 1) {
     load_kf<NX, NU, F>(I, S);
     r_cold = kkt_residual<NX, NU, F, NRTO_DR>(I, S, o, o.sigma_s, false, W);
   }
@@ -1804,7 +1804,7 @@ warm_kernel(DevPtrs g, SolveOpts o, const int32_t* order, int n, const float* pr
   // be removed by the DR iteration's slowest mode.
   const float* pr = pred + (int64_t)ii * ld;
   for (int i = threadIdx.x; i < T * NU; i += blockDim.x) I.du[i] = (double)pr[i];
-  pr += T * NU * (NX + 1);
+  pr += (test & 2) ? T * NU : T * NU * (NX + 1);   // bit 1: the row carries no gains
   for (int c = threadIdx.x; c < I.ng; c += blockDim.x) {
     const double pi = fmax(0.0, (double)pr[I.ng + c]);
     I.C(CA_PT, c) = (double)pr[c];   // the predicted p~, made cone-feasible by warm_pass
@@ -1827,8 +1827,8 @@ warm_kernel(DevPtrs g, SolveOpts o, const int32_t* order, int n, const float* pr
   warm_pass<NX, NU, F>(I, S, o);
   __syncthreads();
   double r_warm = 0.0;
-  if (test) r_warm = kkt_residual<NX, NU, F, NRTO_DR>(I, S, o, o.sigma_s, false, W);
-  const bool keep = !test || r_warm <= r_cold;
+  if (test & 1) r_warm = kkt_residual<NX, NU, F, NRTO_DR>(I, S, o, o.sigma_s, false, W);
+  const bool keep = !(test & 1) || r_warm <= r_cold;
   if (!keep) cold_state<NX, NU, F, NRTO_DR>(I, S, o);
   if (threadIdx.x == 0) {
     accepted[ii] = keep ? 1 : 0;

@@ -4,9 +4,9 @@ Pipeline (all numerics in libnrto: solves, network forward/backward/Adam,
 warm-start reconstruction and the fallback test):
   1. generate: solve the first successive-linearisation SOCP of seeded
      training problems with the plain batched method (cold start) and keep
-     (features, du, K, p~, pi) of the converged ones;
+     (features, du, p~, pi) of the converged ones;
   2. train: standardise features and targets, then Adam steps of the GELU MLP
-     64 -> 256 x 4 -> 3800 on the GPU;
+     64 -> 256 x 4 -> 1400 on the GPU;
   3. warm-started solves: network inference -> nrto_warm_start (DR fixed-point
      reconstruction, cold fallback when the warm KKT residual is worse) ->
      nrto_solve_socp continuing from that state.
@@ -31,7 +31,9 @@ import synth  # noqa: E402
 
 from . import nrto  # noqa: E402
 
-WIDTHS = [64, 256, 256, 256, 256, 3800]
+# output: du (T*nu = 200), p~ (n_g = 600), pi (n_g) of the quadrotor SOCP; the gains
+# are not predicted (the warm start keeps the cold point's gains)
+WIDTHS = [64, 256, 256, 256, 256, 1400]
 
 
 def dr_options(**kw):
@@ -51,14 +53,14 @@ def features(probs):
 
 
 def solve_batch(probs, opt, stream=None):
-    """Cold batched solve; returns (targets (n x 3800), reports)."""
+    """Cold batched solve; returns (targets (n x 1400): du, p~, pi; reports)."""
     ctx = nrto.Context(probs, opt, stream=stream)
     ctx.linearize()
     rep = ctx.solve()
     rows = []
     for i in range(ctx.n):
         s = ctx.solution(i)
-        rows.append(np.concatenate([s["du"], s["K"].ravel(), s["pt"], s["pi"]]))
+        rows.append(np.concatenate([s["du"], s["pt"], s["pi"]]))
     ctx.close()
     return np.array(rows, dtype=np.float32), rep
 
@@ -106,7 +108,13 @@ def save(net, norm, path):
     flat = {f"W{l}": W for l, (W, b) in enumerate(params)}
     flat.update({f"b{l}": b for l, (W, b) in enumerate(params)})
     xm, xs, ym, ys = norm
-    np.savez_compressed(path, xm=xm, xs=xs, ym=ym, ys=ys, widths=np.array(WIDTHS), **flat)
+    np.savez_compressed(path, xm=xm, xs=xs, ym=ym, ys=ys, widths=np.array(WIDTHS), gains=np.array(0), **flat)
+
+
+def rows_have_gains(path) -> bool:
+    """Whether the network at path predicts K (rows du, K, p~, pi) or not (du, p~, pi)."""
+    d = np.load(path, allow_pickle=False)
+    return bool(d["gains"]) if "gains" in d.files else True
 
 
 def load_net(path, max_batch=4096):

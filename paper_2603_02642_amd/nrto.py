@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libnrto.so")
 NRTO_OK, NRTO_MAXITER, NRTO_INFEASIBLE, NRTO_FALLBACK_COLD = 0, 1, 2, 3
 NRTO_DR, NRTO_FULLADMM = 0, 1
 NRTO_FP64, NRTO_FP32 = 0, 1
+NRTO_WS_NO_GAINS = 2
 
 _dp = C.POINTER(C.c_double)
 
@@ -256,12 +257,14 @@ class Context:
         arrs = [f(a) for a in (st, nu, kt, ptt, du, K, p, pt, lam)]
         _check(load().nrto_set_state(self.h, i, *[_ptr(a) for a in arrs]), self.h)
 
-    def warm_start(self, pred, ld=None, fallback_test=True):
-        """Set the NRTO-DR state from prediction rows (torch float32 tensor on the GPU)."""
+    def warm_start(self, pred, ld=None, fallback_test=True, gains=True):
+        """Set the NRTO-DR state from prediction rows (torch float32 tensor on the GPU);
+        gains=False: rows hold du, p~, pi only."""
         acc = np.zeros(self.n, dtype=np.int32)
         res = np.zeros(2 * self.n)
         ld = pred.shape[1] if ld is None else ld
-        _check(load().nrto_warm_start(self.h, C.c_void_p(pred.data_ptr()), ld, 1 if fallback_test else 0,
+        flags = (1 if fallback_test else 0) | (0 if gains else NRTO_WS_NO_GAINS)
+        _check(load().nrto_warm_start(self.h, C.c_void_p(pred.data_ptr()), ld, flags,
                                       acc.ctypes.data_as(C.POINTER(C.c_int32)), _ptr(res)), self.h)
         return acc, res.reshape(self.n, 2)
 

@@ -39,7 +39,7 @@ def test_learned_pipeline_small():
     ctx = nrto.Context(probs, opt)
     ctx.linearize()
     pred = net.infer(torch.from_numpy(L.features(probs)).cuda())
-    acc, res = ctx.warm_start(pred)
+    acc, res = ctx.warm_start(pred, gains=False)
     assert acc.shape == (16,) and np.all(np.isfinite(res))
     # the fallback keeps the cold point exactly where the warm one is worse
     assert np.all((acc == 1) == (res[:, 0] <= res[:, 1]))
@@ -58,7 +58,7 @@ def test_trained_network_gain_over_cold_start():
     cold = ctx.solve()
     net = L.load_net(WEIGHTS, max_batch=64)
     pred = net.infer(torch.from_numpy(L.features(probs)).cuda())
-    acc, res = ctx.warm_start(pred)
+    acc, res = ctx.warm_start(pred, gains=L.rows_have_gains(WEIGHTS))
     warm = ctx.solve(warm=True)
     ok_c = np.array([r.kkt <= 1e-4 for r in cold])
     ok_w = np.array([r.kkt <= 1e-4 for r in warm])
