@@ -99,7 +99,7 @@ struct WaveTask {
   int32_t len;     // entries
 };
 
-enum { ISCR_PSI = 0, ISCR_KKT, ISCR_RP, ISCR_RD, ISCR_MUHINT, ISCR_SIGMA, ISCR_N = 8 };
+enum { ISCR_PSI = 0, ISCR_KKT, ISCR_RP, ISCR_RD, ISCR_MUHINT, ISCR_N = 8 };
 
 struct SolveOpts {
   int32_t method, precision, max_admm, max_inner, check_every, warm, cold_init, rho_adapt;

@@ -63,7 +63,7 @@ def test_dr_iterates_match_oracle_fp64(T, L, M, alpha, extra):
     assert rep[0].rho == info["rho"]
     if extra.get("rho_adapt"):
         assert info["rho"] != ox["rho"]        # the balancing acted within L iterations
-    print("sigma", rep[0].sigma_s, info["sigma_s"], "updates", rep[0].sigma_updates, info.get("sigma_updates"), flush=True)
+    assert rep[0].sigma_updates == info["sigma_updates"]
     assert abs(rep[0].sigma_s - info["sigma_s"]) <= 1e-9 * info["sigma_s"]
     if extra.get("sigma_adapt"):
         assert info["sigma_s"] != ox["sigma_s"]
