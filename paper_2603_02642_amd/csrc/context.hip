@@ -62,6 +62,8 @@ struct nrto_ctx_s {
   double* scp_out = nullptr;   // 5 per instance: merit-test results of nrto_scp_step
   double us_per_tick = 0.0;    // device wall clock period in microseconds
   hipGraphExec_t step_exec = nullptr;  // captured linearise + solve (nrto_capture_step)
+  hipStream_t aux[2] = {nullptr, nullptr};  // the second and third model groups' solve launches
+  hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
   int32_t* ws_acc = nullptr;   // nrto_warm_start: accepted flag per instance
   double* ws_res = nullptr;    // nrto_warm_start: (warm, cold) residual per instance
 };
@@ -492,6 +494,19 @@ extern "C" nrto_status nrto_setup(const nrto_problem* probs, int32_t n, const nr
   HIPCHK(c, hipStreamSynchronize(sm));
   s = configure_launch(c);
   if (s != NRTO_OK) { g_err = c->err; nrto_destroy(c); return s; }
+  // side streams (default priority) for the solve launches of the other model groups
+  {
+    hipError_t e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+    for (int j = 0; j < 2 && e == hipSuccess; ++j) {
+      e = hipStreamCreateWithFlags(&c->aux[j], hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join[j], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+      ctx_err(c, NRTO_ERR_HIP, std::string("side streams: ") + hipGetErrorString(e));
+      nrto_destroy(c);
+      return NRTO_ERR_HIP;
+    }
+  }
   {
     int dev = 0, khz = 0;
     if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess &&
@@ -507,6 +522,11 @@ extern "C" void nrto_destroy(nrto_ctx c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
   if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
+  for (int j = 0; j < 2; ++j) {
+    if (c->aux[j]) (void)hipStreamDestroy(c->aux[j]);
+    if (c->ev_join[j]) (void)hipEventDestroy(c->ev_join[j]);
+  }
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   for (void* p : c->allocs) hipFree(p);
   delete c;
 }
@@ -586,6 +606,30 @@ extern "C" nrto_status nrto_download_socp(nrto_ctx c, int32_t inst, double* A, d
   return NRTO_OK;
 }
 
+// Solve launches of all model groups: the first non-empty group on the context's
+// stream, the others on side streams forked from and joined back into it, so
+// that the groups' persistent launches overlap (their tails in particular).
+static nrto_status launch_solve(nrto_ctx c, int warm) {
+  SolveOpts o;
+  fill_opts(c, o, warm);
+  int groups[3], ng = 0;
+  for (int gi = 0; gi < 3; ++gi)
+    if (c->group_off[gi + 1] > c->group_off[gi]) groups[ng++] = gi;
+  if (ng > 1) HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
+  for (int j = 0; j < ng; ++j) {
+    const int gi = groups[j];
+    hipStream_t s = (j == 0) ? c->stream : c->aux[j - 1];
+    if (j > 0) HIPCHK(c, hipStreamWaitEvent(s, c->ev_fork, 0));
+    const int cnt = c->group_off[gi + 1] - c->group_off[gi];
+    HIPCHK(c, launch_solver(c->g, o, c->group_nx[gi], c->order + c->group_off[gi], cnt, c->threads, c->smem, s));
+    if (j > 0) {
+      HIPCHK(c, hipEventRecord(c->ev_join[j - 1], s));
+      HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join[j - 1], 0));
+    }
+  }
+  return NRTO_OK;
+}
+
 extern "C" nrto_status nrto_solve_socp(nrto_ctx c, int32_t warm, nrto_solve_report* rep) {
   if (!c) return set_global_error(NRTO_ERR_ARG, "null context");
   if (c->opt.method == NRTO_FULLADMM)
@@ -596,13 +640,8 @@ extern "C" nrto_status nrto_solve_socp(nrto_ctx c, int32_t warm, nrto_solve_repo
     return ctx_err(c, NRTO_ERR_STATE,
                    "the FP32 solver path is switched off: its kernel took a GPU memory fault whose cause is not "
                    "yet identified; use NRTO_FP64");
-  SolveOpts o;
-  fill_opts(c, o, warm ? 1 : 0);
-  for (int gi = 0; gi < 3; ++gi) {
-    const int cnt = c->group_off[gi + 1] - c->group_off[gi];
-    HIPCHK(c, launch_solver(c->g, o, c->group_nx[gi], c->order + c->group_off[gi], cnt, c->threads, c->smem,
-                            c->stream));
-  }
+  nrto_status ls = launch_solve(c, warm ? 1 : 0);
+  if (ls != NRTO_OK) return ls;
   if (rep) {
     HIPCHK(c, copy_out(rep, c->g.rep, (size_t)c->n, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -737,16 +776,6 @@ extern "C" nrto_status nrto_get_nominal(nrto_ctx c, int32_t inst, double* uhat, 
   return NRTO_OK;
 }
 
-static nrto_status launch_solve(nrto_ctx c, int warm) {
-  SolveOpts o;
-  fill_opts(c, o, warm ? 1 : 0);
-  for (int gi = 0; gi < 3; ++gi) {
-    const int cnt = c->group_off[gi + 1] - c->group_off[gi];
-    HIPCHK(c, launch_solver(c->g, o, c->group_nx[gi], c->order + c->group_off[gi], cnt, c->threads, c->smem,
-                            c->stream));
-  }
-  return NRTO_OK;
-}
 
 extern "C" nrto_status nrto_capture_step(nrto_ctx c, int32_t warm, int32_t with_linearize) {
   if (!c) return set_global_error(NRTO_ERR_ARG, "null context");
