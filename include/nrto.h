@@ -26,7 +26,11 @@
  *    stream has executed the work.
  *  - A context is bound to one HIP stream (the one given to nrto_setup) and is
  *    not thread-safe.  Calls enqueue work on that stream; calls that return
- *    results to host memory synchronise the stream.
+ *    results to host memory synchronise the stream.  When a context holds
+ *    instances of more than one dynamics model, the solve launches of the
+ *    second and third model run on two non-blocking streams the context owns,
+ *    forked from and joined back into the bound stream with events, so work
+ *    queued after a call on the bound stream still sees its results.
  *  - Arrays are row-major float64 unless stated.  Gains K_k (n_u x n_x) are
  *    returned as K[k][u][x]; the paper's k_v stacks vec(K_k) column-major.
  *
