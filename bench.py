@@ -130,8 +130,8 @@ def main():
                     help="only run a device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; how the path would shard over GPUs is "
-                                   "a design note, not a code path"}))
+        print(json.dumps({"error": f"--gpus {args.gpus}: the solver runs on one GPU; sharding instances "
+                                   "over several GPUs is designed but not implemented"}))
         sys.exit(2)
 
     import torch
