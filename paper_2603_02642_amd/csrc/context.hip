@@ -328,7 +328,7 @@ static nrto_status check_options(nrto_ctx c, const nrto_options* o) {
 static nrto_status configure_launch(nrto_ctx c) {
   int th = c->opt.block_threads;
   if (th == 0) th = (c->n <= 64) ? 512 : 256;
-  if (th > 512) return ctx_err(c, NRTO_ERR_ARG, "block_threads above 512 is not supported by this build");
+  if (th > 512) return ctx_err(c, NRTO_ERR_ARG, "block_threads above 512 exceeds the solver kernels' launch bound of 512 work-items");
   size_t smem = 0;
   for (auto& h : c->hi) smem = std::max(smem, solver_smem_bytes(h.d.T, h.d.nx, h.d.nu, c->opt.precision, th));
   if (smem > 160 * 1024) return ctx_err(c, NRTO_ERR_ARG, "per-instance LDS need exceeds 160 KB (reduce T or use FP32)");
