@@ -182,3 +182,35 @@ def test_captured_step_replays_match_eager():
     c.set_options(o)             # drops the captured step
     with pytest.raises(nrto.NrtoError):
         c.launch_step()
+
+
+@pytest.mark.parametrize("L,M,policy", [(3, 10, False), (4, 12, True)])
+def test_arm_dr_iterates_match_oracle_fp64(L, M, policy):
+    """The 7-DOF arm (n_x = 14, n_u = 7, four obstacles tested at seven link
+    points, joint and torque bounds) on a short horizon: fixed-count iterates of
+    the device solver against the oracle, with the zero starting point or with
+    the margin starting point and sigma_s balancing."""
+    _torch()
+    prob = synth.config3()
+    prob.T = 6
+    prob.u_init = prob.u_init[:6]
+    s = linearize.assemble(prob, prob.u_init, 5.0)
+    if policy:
+        ox = dict(rho=50.0, sigma_s=100.0, sigma_every=3, sigma_thr=1.2)
+        o = dr.Options(max_admm=L, max_dr=M, eps_kkt=0.0, eps_dr_abs=0.0, eps_dr_rel=0.0, cold_init="margin",
+                       sigma_adapt=True, **ox)
+        extra = dict(cold_init=1, sigma_adapt=1, **ox)
+    else:
+        o = dr.Options(max_admm=L, max_dr=M, eps_kkt=0.0, eps_dr_abs=0.0, eps_dr_rel=0.0, rho=40.0, sigma_s=1.0)
+        extra = dict(rho=40.0, sigma_s=1.0)
+    st, info = dr.solve(s, o)
+    c = _ctx(prob, s, method=0, max_admm=L, max_inner=M, eps_kkt=0.0, eps_dr_abs=0.0, eps_dr_rel=0.0,
+             r_trust=5.0, **extra)
+    rep = c.solve()
+    g = c.solution(0)
+    assert rep[0].admm_iters == L and rep[0].inner_iters == L * M
+    assert rep[0].sigma_updates == info["sigma_updates"]
+    for k in ["du", "K", "p", "pt", "lam"]:
+        assert rel_err(g[k], getattr(st, k)) <= 1e-9, k
+    ref_kkt = dr.residual(s, o, st)
+    assert abs(rep[0].kkt - ref_kkt) <= 1e-9 * max(1.0, ref_kkt)
