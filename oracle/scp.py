@@ -13,7 +13,9 @@ where J is the nominal cost on the nonlinear rollout, Q_u its linearisation,
 n_j = ||A_hat_j k_v + b_hat_j|| the robust margin of the new gains (the same
 in all three, so the ratio measures how well the linearised nominal
 trajectory predicts the nonlinear one).  ratio = (cur - act) / (cur - pred);
-accept if the predicted decrease is positive and ratio >= 0.1; on acceptance
+accept if the inner solve reached its tolerance, the predicted decrease is
+positive and ratio >= 0.1 (a step whose SOCP was not solved is never taken: its
+du is not the minimiser the ratio test presumes); on acceptance
 u_hat += du and the radius grows by 1.5 when ratio >= 0.75; on rejection it
 shrinks by 0.8 (not below r_min).  Parity unpinned beyond the GPU comparison:
 the paper prints no outer-loop trace.
@@ -91,7 +93,7 @@ def step(prob, uhat, r_trust, method="dr", opt=None):
     act = J1 + W_P * float(np.sum(np.maximum(0.0, g1 + n)))
     dpred = cur - pred
     ratio = (cur - act) / dpred if dpred > 0 else -np.inf
-    accepted = bool(dpred > 0 and ratio >= ETA_ACCEPT)
+    accepted = bool(info["status"] == "ok" and dpred > 0 and ratio >= ETA_ACCEPT)
     if accepted:
         r_new = min(GROW * r_trust, R_MAX) if ratio >= ETA_GROW else r_trust
     else:

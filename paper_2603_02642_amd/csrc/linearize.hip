@@ -333,7 +333,8 @@ __global__ void cone_data_kernel(DevPtrs g, int n_inst) {
 }
 
 // Trust-region test of one successive-linearisation step (see the oracle's scp
-// module for the merit definitions).  One workgroup per instance; out[4*ii..]
+// module for the merit definitions).  A step whose SOCP solve did not reach its
+// tolerance is rejected (the radius shrinks).  One workgroup per instance; out[4*ii..]
 // receives (accepted, merit_cur, merit_act, merit_pred).
 template <int NX, int NU>
 __device__ void scp_eval(const DevPtrs& g, int ii, double w_p, double* out) {
@@ -425,7 +426,7 @@ __device__ void scp_eval(const DevPtrs& g, int ii, double w_p, double* out) {
     }
     const double dpred = cur - pred;
     const double ratio = dpred > 0.0 ? (cur - act) / dpred : -1e300;
-    const bool acc = dpred > 0.0 && ratio >= 0.1;
+    const bool acc = g.rep[ii].status == NRTO_OK && dpred > 0.0 && ratio >= 0.1;
     double r = d.r_trust;
     if (acc) {
       if (ratio >= 0.75) r = fmin(1.5 * r, 1e3);

@@ -1464,6 +1464,7 @@ __device__ void zero_state(const Inst<NX, NU, F>& I) {
     *I.mu = 0.0;
     I.flags[0] = 0;
     I.iscr[ISCR_PSI] = 0.0;
+    I.iscr[ISCR_MUHINT] = 0.0;   // a cold solve keeps nothing from earlier solves
   }
   __syncthreads();
 }
