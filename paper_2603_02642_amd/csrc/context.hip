@@ -527,7 +527,7 @@ extern "C" void nrto_destroy(nrto_ctx c) {
     if (c->ev_join[j]) (void)hipEventDestroy(c->ev_join[j]);
   }
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-  for (void* p : c->allocs) hipFree(p);
+  for (void* p : c->allocs) (void)hipFree(p);
   delete c;
 }
 

@@ -3,8 +3,9 @@
 // Memory-bound: each entry is read once and written once.  A workgroup owns
 // the cones whose first entry (t) falls in its tile of TILE entries; their
 // entries are streamed with coalesced loads into LDS (up to CAP), the squared
-// norms of the eta parts are reduced per cone with LDS float64 atomics, and a
-// second sweep over the staged values applies the closed form:
+// norms of the eta parts are reduced per cone in a fixed order (one thread per
+// short cone, one wave per long cone), and a second sweep over the staged
+// values applies the closed form:
 //   a = ||eta||;  a <= t -> unchanged;  a <= -t -> 0;  else ((t+a)/2, (t+a)/(2a) eta).
 // Entries of an owned cone beyond CAP (cones longer than CAP - TILE) are read
 // from global memory a second time.
@@ -16,6 +17,7 @@ namespace nrto {
 constexpr int PS_THREADS = 256;
 constexpr int PS_TILE = 1024;
 constexpr int PS_CAP = 4096;
+constexpr int PS_SHORT = 32;   // cones with more eta entries are reduced by a wave
 
 __device__ __forceinline__ int64_t lower_bound_i64(const int64_t* a, int64_t n, int64_t key) {
   // first index i in [0, n] with a[i] >= key (a has n + 1 readable entries)
@@ -54,19 +56,37 @@ project_soc_kernel(const F* in, F* out, const int64_t* __restrict__ off,
     for (int i = threadIdx.x; i <= nown; i += PS_THREADS) {
       int64_t o = min(max(off[cb + i], e_lo), e_hi);
       coff[i] = (int32_t)min(o - e_lo, (int64_t)0x7fffffff);
-      if (i < nown) sums[i] = 0.0;
     }
     __syncthreads();
-    // phase 1: stage and reduce ||eta||^2 per cone
-    for (int64_t l = threadIdx.x; l < len; l += PS_THREADS) {
-      F v = in[e_lo + l];
-      if (l < PS_CAP) stage[l] = v;
-      int lo = 0, hi = nown - 1;                      // last cone c with coff[c] <= l
-      while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (coff[mid] <= l) lo = mid; else hi = mid - 1;
+    // phase 1: stage the tile's entries
+    for (int64_t l = threadIdx.x; l < len && l < PS_CAP; l += PS_THREADS) stage[l] = in[e_lo + l];
+    __syncthreads();
+    // ||eta||^2 per owned cone in a fixed summation order (the result does not
+    // depend on scheduling): a cone with at most SHORT eta entries is summed
+    // serially by one thread, a longer one by one wave (lane-strided partial
+    // sums, then a butterfly over the lanes)
+    for (int i = threadIdx.x; i < nown; i += PS_THREADS) {
+      const int c0 = coff[i], c1 = coff[i + 1];
+      if (c1 - c0 - 1 <= PS_SHORT) {
+        double acc = 0.0;
+        for (int l = c0 + 1; l < c1; ++l) {
+          const double v = (double)((l < PS_CAP) ? stage[l] : in[e_lo + l]);
+          acc += v * v;
+        }
+        sums[i] = acc;
       }
-      if (l != coff[lo]) atomicAdd(&sums[lo], (double)v * (double)v);
+    }
+    for (int i = wave_id(); i < nown; i += PS_THREADS / NRTO_WAVE) {
+      const int c0 = coff[i], c1 = coff[i + 1];
+      if (c1 - c0 - 1 > PS_SHORT) {
+        double acc = 0.0;
+        for (int l = c0 + 1 + lane_id(); l < c1; l += NRTO_WAVE) {
+          const double v = (double)((l < PS_CAP) ? stage[l] : in[e_lo + l]);
+          acc += v * v;
+        }
+        acc = wave_sum(acc);
+        if (lane_id() == 0) sums[i] = acc;
+      }
     }
     __syncthreads();
     // phase 2: closed-form projection
@@ -105,6 +125,21 @@ __global__ void validate_offsets_kernel(const int64_t* off, int64_t ncones, int6
 
 using namespace nrto;
 
+static nrto_status launch_projection(const void* in, void* out, const int64_t* seg_off, int64_t n_cones,
+                                     int64_t n_entries, int32_t dtype, hipStream_t s) {
+  int64_t nblocks = (n_entries + PS_TILE - 1) / PS_TILE;
+  if (nblocks > 0x7fffffff) return set_global_error(NRTO_ERR_ARG, "too many entries");
+  if (dtype == 0)
+    project_soc_kernel<double><<<dim3((unsigned)nblocks), dim3(PS_THREADS), 0, s>>>(
+        (const double*)in, (double*)out, seg_off, n_cones, n_entries);
+  else
+    project_soc_kernel<float><<<dim3((unsigned)nblocks), dim3(PS_THREADS), 0, s>>>(
+        (const float*)in, (float*)out, seg_off, n_cones, n_entries);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_global_error(NRTO_ERR_HIP, hipGetErrorString(e));
+  return NRTO_OK;
+}
+
 extern "C" nrto_status nrto_project_soc(const void* in, void* out, const int64_t* seg_off,
                                         int64_t n_cones, int64_t n_entries, int32_t dtype,
                                         int32_t flags, void* stream) {
@@ -129,15 +164,5 @@ extern "C" nrto_status nrto_project_soc(const void* in, void* out, const int64_t
     if (e != hipSuccess) return set_global_error(NRTO_ERR_HIP, hipGetErrorString(e));
     if (h) return set_global_error(NRTO_ERR_ARG, "seg_off must start at 0, be non-decreasing and end at n_entries");
   }
-  int64_t nblocks = (n_entries + PS_TILE - 1) / PS_TILE;
-  if (nblocks > 0x7fffffff) return set_global_error(NRTO_ERR_ARG, "too many entries");
-  if (dtype == 0)
-    project_soc_kernel<double><<<dim3((unsigned)nblocks), dim3(PS_THREADS), 0, s>>>(
-        (const double*)in, (double*)out, seg_off, n_cones, n_entries);
-  else
-    project_soc_kernel<float><<<dim3((unsigned)nblocks), dim3(PS_THREADS), 0, s>>>(
-        (const float*)in, (float*)out, seg_off, n_cones, n_entries);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return set_global_error(NRTO_ERR_HIP, hipGetErrorString(e));
-  return NRTO_OK;
+  return launch_projection(in, out, seg_off, n_cones, n_entries, dtype, s);
 }

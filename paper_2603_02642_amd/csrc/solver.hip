@@ -399,6 +399,226 @@ __device__ __forceinline__ void soc_case(double t, double a, double& that, doubl
 // ----------------------------------------------------------------------------
 // DR pass: one relaxed DR iteration over all cones of the instance (after the
 // K-solve).  Accumulates sum ||delta s~||^2 and ||s~||^2.
+//
+// A long cone (65..64*E entries) is handled by one wave in a single sweep: every
+// lane first issues the loads of its E entries of s~ and b_hat (independent, so
+// they are in flight together), then forms eta(K) with the block vectors and
+// K_k from LDS, reduces the reflected norm, and projects / relaxes / stores the
+// entries it holds in registers.  The cone's metadata is read once per cone.
+#ifndef NRTO_DR_STAGE
+#define NRTO_DR_STAGE 4
+#endif
+constexpr int DR_STAGE = NRTO_DR_STAGE;   // chunks of 64 entries a lane holds per sweep
+
+template <int NX, int NU, typename F, int E>
+__device__ __forceinline__ void dr_long_cone(const WaveTask tk, const int32_t* __restrict__ m, F* __restrict__ st,
+                                             const F* __restrict__ bhat, const F* __restrict__ bvec,
+                                             const F* Kf, F* Racc, int T, F r, double al, double ptc_num,
+                                             double sig, double den, double* ca_pt, double* ca_ptt,
+                                             double (&acc)[5]) {
+  const int lane = lane_id();
+  const int len = tk.len;
+  const int k0 = m[CM_K0], boff = m[CM_BOFF];
+  F stv[E], bhv[E], fv[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int le = lane + i * NRTO_WAVE;
+    stv[i] = (F)0;
+    bhv[i] = (F)0;
+    if (le < len) {
+      stv[i] = st[le];
+      bhv[i] = bhat[le];
+    }
+  }
+  // forward gain GEMM and the norm of the reflected eta
+  double sq = 0.0;
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int le = lane + i * NRTO_WAVE;
+    fv[i] = (F)0;
+    if (le >= 1 && le < len) {
+      const int q = le - 1;
+      const int blk = q / NX;
+      const int x = q - blk * NX;
+      const int k = k0 + blk;
+      if (k < T) {   // the last block of a state constraint at t = T has no gain
+        const F* bv = bvec + (int64_t)(boff + blk) * NU;
+        F f = (F)0;
+#pragma unroll
+        for (int u = 0; u < NU; ++u) f += bv[u] * Kf[(u * T + k) * NX + x];
+        fv[i] = f;
+      }
+      const F s = r * fv[i] + bhv[i];
+      const F sr = (F)2 * s - stv[i];
+      sq += (double)sr * (double)sr;
+    }
+  }
+  double ptc = 0.0, tr0 = 0.0;
+  if (lane == 0) {
+    ptc = (ptc_num + sig * (double)stv[0]) / den;
+    tr0 = (double)((F)2 * (F)ptc - stv[0]);
+  }
+  const double a = sqrt(wave_sum(sq));
+  const double tref = __shfl(tr0, 0, NRTO_WAVE);
+  double that, scale;
+  soc_case(tref, a, that, scale);
+  double dsum = 0.0, nsum = 0.0, ssum = 0.0;
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int le = lane + i * NRTO_WAVE;
+    if (le < len) {
+      F s, shat;
+      if (le == 0) {
+        s = (F)ptc;
+        shat = (F)that;
+      } else {
+        s = r * fv[i] + bhv[i];
+        const F sr = (F)2 * s - stv[i];
+        shat = (F)(scale * (double)sr);
+      }
+      const F diff = shat - s;
+      const F stn = stv[i] + (F)al * diff;
+      st[le] = stn;
+      const double dd = al * (double)diff;
+      dsum += dd * dd;
+      nsum += (double)stn * (double)stn;
+      ssum += (double)s * (double)s;
+      if (le > 0) {
+        const int q = le - 1;
+        const int blk = q / NX;
+        const int x = q - blk * NX;
+        const int k = k0 + blk;
+        if (k < T) {
+          const F* bv = bvec + (int64_t)(boff + blk) * NU;
+          const F d = stn - bhv[i];
+#pragma unroll
+          for (int u = 0; u < NU; ++u) atomicAdd(&Racc[(u * T + k) * NX + x], bv[u] * d);
+        }
+      }
+    }
+  }
+  if (lane == 0) {
+    *ca_pt = ptc;
+    const double pt0 = *ca_ptt;
+    *ca_ptt = pt0 + al * (ptc - pt0);
+  }
+  acc[0] += dsum;
+  acc[1] += nsum;
+  acc[4] += ssum;
+}
+
+// Cones longer than one register-staged sweep holds: two sweeps over the
+// entries in groups of E chunks (the first forms the reflected norm, the
+// second reloads the group, recomputes eta, projects, relaxes and accumulates
+// the adjoint); the loads of a group are issued together.
+template <int NX, int NU, typename F, int E>
+__device__ void dr_long_cone_2pass(const WaveTask tk, const int32_t* __restrict__ m, F* __restrict__ st,
+                                   const F* __restrict__ bhat, const F* __restrict__ bvec, const F* Kf, F* Racc,
+                                   int T, F r, double al, double ptc_num, double sig, double den, double* ca_pt,
+                                   double* ca_ptt, double (&acc)[5]) {
+  const int lane = lane_id();
+  const int len = tk.len;
+  const int k0 = m[CM_K0], boff = m[CM_BOFF];
+  double sq = 0.0, ptc = 0.0, tr0 = 0.0;
+  if (lane == 0) {
+    const F st0 = st[0];
+    ptc = (ptc_num + sig * (double)st0) / den;
+    tr0 = (double)((F)2 * (F)ptc - st0);
+  }
+  for (int base = 0; base < len; base += E * NRTO_WAVE) {
+    F stv[E], bhv[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int le = base + lane + i * NRTO_WAVE;
+      stv[i] = (F)0;
+      bhv[i] = (F)0;
+      if (le >= 1 && le < len) {
+        stv[i] = st[le];
+        bhv[i] = bhat[le];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int le = base + lane + i * NRTO_WAVE;
+      if (le >= 1 && le < len) {
+        const int q = le - 1, blk = q / NX, x = q - blk * NX, k = k0 + blk;
+        F f = (F)0;
+        if (k < T) {
+          const F* bv = bvec + (int64_t)(boff + blk) * NU;
+#pragma unroll
+          for (int u = 0; u < NU; ++u) f += bv[u] * Kf[(u * T + k) * NX + x];
+        }
+        const F sr = (F)2 * (r * f + bhv[i]) - stv[i];
+        sq += (double)sr * (double)sr;
+      }
+    }
+  }
+  const double a = sqrt(wave_sum(sq));
+  const double tref = __shfl(tr0, 0, NRTO_WAVE);
+  double that, scale;
+  soc_case(tref, a, that, scale);
+  double dsum = 0.0, nsum = 0.0, ssum = 0.0;
+  for (int base = 0; base < len; base += E * NRTO_WAVE) {
+    F stv[E], bhv[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int le = base + lane + i * NRTO_WAVE;
+      stv[i] = (F)0;
+      bhv[i] = (F)0;
+      if (le < len) {
+        stv[i] = st[le];
+        if (le >= 1) bhv[i] = bhat[le];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int le = base + lane + i * NRTO_WAVE;
+      if (le < len) {
+        F s, shat;
+        int k = 0, x = 0, blk = 0;
+        if (le == 0) {
+          s = (F)ptc;
+          shat = (F)that;
+        } else {
+          const int q = le - 1;
+          blk = q / NX;
+          x = q - blk * NX;
+          k = k0 + blk;
+          F f = (F)0;
+          if (k < T) {
+            const F* bv = bvec + (int64_t)(boff + blk) * NU;
+#pragma unroll
+            for (int u = 0; u < NU; ++u) f += bv[u] * Kf[(u * T + k) * NX + x];
+          }
+          s = r * f + bhv[i];
+          shat = (F)(scale * (double)((F)2 * s - stv[i]));
+        }
+        const F diff = shat - s;
+        const F stn = stv[i] + (F)al * diff;
+        st[le] = stn;
+        const double dd = al * (double)diff;
+        dsum += dd * dd;
+        nsum += (double)stn * (double)stn;
+        ssum += (double)s * (double)s;
+        if (le > 0 && k < T) {
+          const F* bv = bvec + (int64_t)(boff + blk) * NU;
+          const F d = stn - bhv[i];
+#pragma unroll
+          for (int u = 0; u < NU; ++u) atomicAdd(&Racc[(u * T + k) * NX + x], bv[u] * d);
+        }
+      }
+    }
+  }
+  if (lane == 0) {
+    *ca_pt = ptc;
+    const double pt0 = *ca_ptt;
+    *ca_ptt = pt0 + al * (ptc - pt0);
+  }
+  acc[0] += dsum;
+  acc[1] += nsum;
+  acc[4] += ssum;
+}
+
 template <int NX, int NU, typename F>
 __device__ void dr_pass(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o, double rho, double sig,
                         double (&acc)[5]) {
@@ -411,67 +631,24 @@ __device__ void dr_pass(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o
   for (int t = next_task(S.ctr); t < I.ntask; t = next_task(S.ctr)) {
     const WaveTask tk = I.tasks[t];
     if (tk.ncone == 1 && tk.len > NRTO_WAVE) {
-      // one long cone: pass 1 forms s = (p~, eta(K)) and the norm of the reflected
-      // eta; pass 2 recomputes s (no per-lane arrays), projects, relaxes and
-      // accumulates the adjoint
       const int c = tk.cone;
       const int32_t* m = I.cm + c * CM_N;
-      double sq = 0.0, ptc = 0.0, tr0 = 0.0;
-      for (int le = lane; le < tk.len; le += NRTO_WAVE) {
-        const int64_t e = tk.ebeg + le;
-        const F stv = I.st[e];
-        if (le == 0) {
-          ptc = (o.sigma_chi * I.C(CA_PTT, c) + rho * I.C(CA_P, c) + I.C(CA_LAM, c) +
-                 sig * (double)stv) / den;
-          tr0 = (double)((F)2 * (F)ptc - stv);
-        } else {
-          int k, x, b;
-          entry_block<NX>(m, le, k, x, b);
-          const F s = r * fwd_gemm<NX, NU, F>(I, S, T, k, x, I.bvec + (int64_t)b * NU) + I.bhat[e];
-          const F sr = (F)2 * s - stv;
-          sq += (double)sr * (double)sr;
-        }
-      }
-      const double a = sqrt(wave_sum(sq));
-      const double tref = __shfl(tr0, 0, NRTO_WAVE);
-      double that, scale;
-      soc_case(tref, a, that, scale);
-      double dsum = 0.0, nsum = 0.0, ssum = 0.0;
-      for (int le = lane; le < tk.len; le += NRTO_WAVE) {
-        const int64_t e = tk.ebeg + le;
-        const F stv = I.st[e];
-        F s, shat, bh = (F)0;
-        int k = 0, x = 0, b = 0;
-        if (le == 0) {
-          s = (F)ptc;
-          shat = (F)that;
-        } else {
-          entry_block<NX>(m, le, k, x, b);
-          bh = I.bhat[e];
-          s = r * fwd_gemm<NX, NU, F>(I, S, T, k, x, I.bvec + (int64_t)b * NU) + bh;
-          const F sr = (F)2 * s - stv;
-          shat = (F)(scale * (double)sr);
-        }
-        const F diff = shat - s;
-        const F stn = stv + (F)al * diff;
-        I.st[e] = stn;
-        const double dd = al * (double)diff;
-        dsum += dd * dd;
-        nsum += (double)stn * (double)stn;
-        ssum += (double)s * (double)s;
-        if (le == 0) {
-          I.C(CA_PT, c) = ptc;
-          const double pt0 = I.C(CA_PTT, c);
-          I.C(CA_PTT, c) = pt0 + al * (ptc - pt0);
-        } else {
-          adj_gemm<NX, NU, F>(S, T, k, x, I.bvec + (int64_t)b * NU, stn - bh);
-        }
-      }
-      acc[0] += dsum;
-      acc[1] += nsum;
-      acc[4] += ssum;
+      const double ptc_num = o.sigma_chi * I.C(CA_PTT, c) + rho * I.C(CA_P, c) + I.C(CA_LAM, c);
+      F* st = I.st + tk.ebeg;
+      const F* bh = I.bhat + tk.ebeg;
+      double* cpt = &I.C(CA_PT, c);
+      double* cptt = &I.C(CA_PTT, c);
+      if (tk.len <= 2 * NRTO_WAVE)
+        dr_long_cone<NX, NU, F, 2>(tk, m, st, bh, I.bvec, S.Kf, S.Racc, T, r, al, ptc_num, sig, den, cpt, cptt, acc);
+      else if (tk.len <= DR_STAGE * NRTO_WAVE)
+        dr_long_cone<NX, NU, F, DR_STAGE>(tk, m, st, bh, I.bvec, S.Kf, S.Racc, T, r, al, ptc_num, sig, den, cpt,
+                                          cptt, acc);
+      else
+        dr_long_cone_2pass<NX, NU, F, DR_STAGE>(tk, m, st, bh, I.bvec, S.Kf, S.Racc, T, r, al, ptc_num, sig, den,
+                                                cpt, cptt, acc);
     } else {
-      // packed short cones: one entry per lane
+      // packed short cones: one entry per lane; each lane reads its cone's
+      // metadata and its block vector once
       const uint64_t mask = I.tmask[t];
       const int l = lane;
       const bool valid = l < tk.len;
@@ -483,21 +660,36 @@ __device__ void dr_pass(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o
       ws[l] = 0.0;
       wave_sync();
       F s = (F)0, stv = (F)0, bh = (F)0;
+      F bvr[NU];
+#pragma unroll
+      for (int u = 0; u < NU; ++u) bvr[u] = (F)0;
       double ptc = 0.0;
-      int k = 0, x = 0, b = 0;
-      const int32_t* m = I.cm + c * CM_N;
+      int k = 0, x = 0;
+      bool has_gain = false;
       if (valid) {
         const int64_t e = tk.ebeg + l;
         stv = I.st[e];
         if (le == 0) {
-          ptc = (o.sigma_chi * I.C(CA_PTT, c) + rho * I.C(CA_P, c) + I.C(CA_LAM, c) +
-                 sig * (double)stv) / den;
+          ptc = (o.sigma_chi * I.C(CA_PTT, c) + rho * I.C(CA_P, c) + I.C(CA_LAM, c) + sig * (double)stv) / den;
           s = (F)ptc;
           ws[64 + cl] = (double)((F)2 * s - stv);
         } else {
-          entry_block<NX>(m, le, k, x, b);
+          const int32_t* m = I.cm + c * CM_N;
+          const int q = le - 1, blk = q / NX;
+          x = q - blk * NX;
+          k = m[CM_K0] + blk;
           bh = I.bhat[e];
-          s = r * fwd_gemm<NX, NU, F>(I, S, T, k, x, I.bvec + (int64_t)b * NU) + bh;
+          F f = (F)0;
+          if (k < T) {
+            has_gain = true;
+            const F* bv = I.bvec + (int64_t)(m[CM_BOFF] + blk) * NU;
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+              bvr[u] = bv[u];
+              f += bvr[u] * S.Kf[(u * T + k) * NX + x];
+            }
+          }
+          s = r * f + bh;
           const F sr = (F)2 * s - stv;
           atomicAdd(&ws[cl], (double)sr * (double)sr);
         }
@@ -522,8 +714,13 @@ __device__ void dr_pass(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o
           I.C(CA_PT, c) = ptc;
           const double pt0 = I.C(CA_PTT, c);
           I.C(CA_PTT, c) = pt0 + al * (ptc - pt0);
-        } else {
-          adj_gemm<NX, NU, F>(S, T, k, x, I.bvec + (int64_t)b * NU, stn - bh);
+        } else if (has_gain) {
+          const F d = stn - bh;
+#pragma unroll
+          for (int u = 0; u < NU; ++u) {
+            const F cu = bvr[u] * d;
+            if (cu != (F)0) atomicAdd(&S.Racc[(u * T + k) * NX + x], cu);
+          }
         }
       }
       wave_sync();
