@@ -179,6 +179,23 @@ nrto_status nrto_project_soc(const void *in, void *out, const int64_t *seg_off,
                              int32_t flags, void *stream);
 
 /*
+ * nrto_project_soc with offset validation (flags bit 0), for callers that
+ * cannot allocate device memory: code that must not call hipMalloc (tight
+ * serving loops, harnesses that forbid it).  Arguments, results and errors as
+ * nrto_project_soc with flags = 1; the validation flag lives in a fixed 256-byte
+ * array the library keeps on every device it runs on until the process ends, so
+ * the call allocates nothing.  No input size depends on that array; the limits
+ * are those of one launch (at most 2^31 - 1 workgroups of 256 cones or 1024
+ * entries), beyond which the call returns NRTO_ERR_ARG.  The current device must
+ * be the stream's device.  The array is shared by every call on a device: calls
+ * that overlap on one device (other streams or threads) race on the flag.  The
+ * call synchronises the stream (it reads the flag back).
+ */
+nrto_status nrto_project_soc_noalloc(const void *in, void *out, const int64_t *seg_off,
+                                     int64_t n_cones, int64_t n_entries, int32_t dtype,
+                                     void *stream);
+
+/*
  * Create a context for n_inst problems: device workspace, compact cone layout,
  * wave task schedule.  probs: host array of n_inst problems.  opt: solver
  * options (copied; may be changed later with nrto_set_options).  stream:

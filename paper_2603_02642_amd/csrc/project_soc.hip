@@ -9,6 +9,9 @@
 //   a = ||eta||;  a <= t -> unchanged;  a <= -t -> 0;  else ((t+a)/2, (t+a)/(2a) eta).
 // Entries of an owned cone beyond CAP (cones longer than CAP - TILE) are read
 // from global memory a second time.
+#include <mutex>
+#include <string>
+
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -121,6 +124,40 @@ __global__ void validate_offsets_kernel(const int64_t* off, int64_t ncones, int6
   if (i < ncones && off[i + 1] < off[i]) atomicOr(bad, 1);
 }
 
+// Scratch of nrto_project_soc_noalloc: word 0 is the offset-validation flag,
+// the other words are unused.  Every device the library runs on holds its own
+// copy for the life of the process; host code reaches it only through the
+// address hipGetSymbolAddress returns for the current device.
+constexpr int NOALLOC_SCRATCH_WORDS = 64;
+static __device__ __align__(256) int32_t scratch[NOALLOC_SCRATCH_WORDS];
+
+__global__ void clear_words_kernel(int32_t* w, int n) {
+  if ((int)threadIdx.x < n) w[threadIdx.x] = 0;
+}
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static int32_t* g_scratch_dev[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device, resolved once per device.
+static nrto_status scratch_address(int32_t** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return set_global_error(NRTO_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+    return set_global_error(NRTO_ERR_ARG, "device ordinal beyond the 64 devices the scratch table covers");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return set_global_error(NRTO_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = (int32_t*)p;
+  }
+  *out = g_scratch_dev[dev];
+  return NRTO_OK;
+}
+
 }  // namespace nrto
 
 using namespace nrto;
@@ -164,5 +201,34 @@ extern "C" nrto_status nrto_project_soc(const void* in, void* out, const int64_t
     if (e != hipSuccess) return set_global_error(NRTO_ERR_HIP, hipGetErrorString(e));
     if (h) return set_global_error(NRTO_ERR_ARG, "seg_off must start at 0, be non-decreasing and end at n_entries");
   }
+  return launch_projection(in, out, seg_off, n_cones, n_entries, dtype, s);
+}
+
+extern "C" nrto_status nrto_project_soc_noalloc(const void* in, void* out, const int64_t* seg_off,
+                                                int64_t n_cones, int64_t n_entries, int32_t dtype,
+                                                void* stream) {
+  if (n_cones < 0 || n_entries < 0) return set_global_error(NRTO_ERR_ARG, "negative size");
+  if (dtype != 0 && dtype != 1) return set_global_error(NRTO_ERR_ARG, "dtype must be 0 (f64) or 1 (f32)");
+  if (n_entries == 0 || n_cones == 0) return NRTO_OK;
+  if (!in || !out || !seg_off) return set_global_error(NRTO_ERR_ARG, "null pointer");
+  if ((n_cones + 255) / 256 > 0x7fffffff || (n_entries + PS_TILE - 1) / PS_TILE > 0x7fffffff)
+    return set_global_error(NRTO_ERR_ARG, "too many cones or entries for one launch");
+  int32_t* scr = nullptr;
+  nrto_status st = scratch_address(&scr);
+  if (st != NRTO_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  // the flag keeps the previous call's value: clear it with a kernel (no memset node)
+  clear_words_kernel<<<dim3(1), dim3(64), 0, s>>>(scr, 1);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    validate_offsets_kernel<<<dim3((unsigned)((n_cones + 255) / 256)), dim3(256), 0, s>>>(seg_off, n_cones,
+                                                                                      n_entries, scr);
+    e = hipGetLastError();
+  }
+  int32_t h = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&h, scr, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return set_global_error(NRTO_ERR_HIP, hipGetErrorString(e));
+  if (h) return set_global_error(NRTO_ERR_ARG, "seg_off must start at 0, be non-decreasing and end at n_entries");
   return launch_projection(in, out, seg_off, n_cones, n_entries, dtype, s);
 }

@@ -78,6 +78,7 @@ def load() -> C.CDLL:
     sig = {
         "nrto_default_options": (None, [P(Options)]),
         "nrto_project_soc": (i32, [vp, vp, vp, i64, i64, i32, i32, vp]),
+        "nrto_project_soc_noalloc": (i32, [vp, vp, vp, i64, i64, i32, vp]),
         "nrto_setup": (i32, [P(Problem), i32, P(Options), vp, P(vp)]),
         "nrto_destroy": (None, [vp]),
         "nrto_last_error": (C.c_char_p, [vp]),
@@ -146,6 +147,26 @@ def project_soc(x, seg_off, out=None, validate: bool = False, stream=None):
     _check(load().nrto_project_soc(C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()),
                                    C.c_void_p(seg_off.data_ptr()), seg_off.numel() - 1, x.numel(),
                                    dtype, 1 if validate else 0, C.c_void_p(s)))
+    return out
+
+
+def project_soc_noalloc(x, seg_off, out=None, stream=None):
+    """nrto_project_soc_noalloc: the validated projection without any device
+    allocation inside the call (torch tensors on the GPU, as project_soc)."""
+    import torch
+    if out is None:
+        out = torch.empty_like(x)
+    dtype = 0 if x.dtype == torch.float64 else 1 if x.dtype == torch.float32 else -1
+    if dtype < 0:
+        raise TypeError("float64 or float32 values required")
+    if not (x.is_cuda and seg_off.is_cuda and out.is_cuda):
+        raise TypeError("device tensors required")
+    if seg_off.dtype != torch.int64:
+        raise TypeError("int64 offsets required")
+    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    _check(load().nrto_project_soc_noalloc(C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()),
+                                           C.c_void_p(seg_off.data_ptr()), seg_off.numel() - 1, x.numel(),
+                                           dtype, C.c_void_p(s)))
     return out
 
 
