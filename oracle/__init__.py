@@ -20,6 +20,8 @@ Contents, each following the passage it cites (cuNRTO, arXiv 2603.02642):
   scp        -- minimal successive-linearisation loop around the solves
   robust     -- closed-form worst case and Monte-Carlo disturbance checks
   mlp        -- FP64 reference MLP (GELU) with backward pass and Adam
+  warm       -- DR state rebuilt from a predicted (du, p~, pi) and the cold
+                fallback test (the learned warm start)
 
 Parity pins live in tests/test_oracle_*.py.  Functions with no pin other than
 the paper's own statement say "parity unpinned" in their docstring.

@@ -8,7 +8,9 @@ squared error over batch and outputs, L = sum (y - t)^2 / (B * D).  Adam
 (Kingma and Ba 2015): m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
 theta -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
 Initial weights uniform in +-sqrt(6 / (fan_in + fan_out)) from SplitMix64,
-biases zero.
+biases zero.  forward / loss_and_grads optionally round every GEMM operand
+(round_bf16: bfloat16, round to nearest even) to model matrix-core products
+of bfloat16 operands; the arithmetic between rounding points stays FP64.
 """
 from __future__ import annotations
 
@@ -39,20 +41,40 @@ def gelu_grad(x):
     return 0.5 * (1.0 + erf(x / math.sqrt(2.0))) + x * np.exp(-0.5 * x * x) / math.sqrt(2.0 * math.pi)
 
 
-def forward(params, X):
-    acts = [X]
+def round_bf16(x):
+    """x rounded to the nearest bfloat16 value (ties to even), as float64: the
+    float32 value of x keeps its top 16 bits after adding half an ulp of the
+    16-bit result (IEEE round-to-nearest-even on an 8-bit significand)."""
+    f = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward(params, X, rnd=None):
+    """rnd: None (exact FP64) or a rounding applied to every GEMM operand (the
+    layer inputs and the weights), as the matrix cores see them."""
+    q = (lambda v: v) if rnd is None else rnd
+    acts = [q(X)]
     pre = []
-    a = X
+    a = acts[0]
     for l, (W, b) in enumerate(params):
-        z = a @ W.T + b
+        z = a @ q(W).T + b
         pre.append(z)
-        a = gelu(z) if l < len(params) - 1 else z
+        if l < len(params) - 1:
+            a = q(gelu(z))
+        else:
+            a = z
         acts.append(a)
     return a, acts, pre
 
 
-def loss_and_grads(params, X, Tgt):
-    Y, acts, pre = forward(params, X)
+def loss_and_grads(params, X, Tgt, rnd=None):
+    """Loss and gradients; with rnd, the backward GEMM operands (the output
+    gradient of each layer and the weights) are rounded too, while the bias
+    gradients sum the unrounded output gradients."""
+    q = (lambda v: v) if rnd is None else rnd
+    Y, acts, pre = forward(params, X, rnd)
     B, D = Y.shape
     diff = Y - Tgt
     loss = float(np.sum(diff * diff) / (B * D))
@@ -62,8 +84,9 @@ def loss_and_grads(params, X, Tgt):
         W, b = params[l]
         if l < len(params) - 1:
             g = g * gelu_grad(pre[l])
-        grads[l] = [g.T @ acts[l], g.sum(axis=0)]
-        g = g @ W
+        gq = q(g)
+        grads[l] = [gq.T @ acts[l], g.sum(axis=0)]
+        g = gq @ q(W)
     return loss, grads
 
 

@@ -366,7 +366,9 @@ extern "C" nrto_status nrto_ws_train_step(nrto_ws ws, const float* X, const floa
   if (st != NRTO_OK) return st;
   ws->t += 1;
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-  const float c1 = 1.f - std::pow(b1, (float)ws->t), c2 = 1.f - std::pow(b2, (float)ws->t);
+  // bias corrections 1 - beta^t in double: in float, 1 - 0.999^2 loses five digits to cancellation
+  const float c1 = (float)(1.0 - std::pow((double)b1, (double)ws->t));
+  const float c2 = (float)(1.0 - std::pow((double)b2, (double)ws->t));
   for (int l = 0; l < ws->L; ++l) {
     const int64_t nw = (int64_t)ws->w[l] * ws->w[l + 1], nb = ws->w[l + 1];
     hipLaunchKernelGGL(adam_kernel, dim3(nblk(nw)), dim3(256), 0, ws->stream, ws->W[l], ws->gW[l], ws->mW[l], ws->vW[l],

@@ -19,6 +19,14 @@
 namespace nrto {
 
 constexpr int EMAX = 16;
+
+// An object in global memory (device allocations).
+template <typename T>
+using G = __attribute__((address_space(1))) T;
+
+// The workgroup's dynamic LDS (one instance's gains, adjoint accumulator,
+// factors, reduction slots and (du, p) scratch).
+extern __shared__ __align__(16) char nrto_dyn_smem[];
 #ifndef NRTO_SOLVER_MAX_THREADS
 #define NRTO_SOLVER_MAX_THREADS 512
 #endif  // entries per lane of a long-cone task (cones up to 1024 entries)
@@ -411,45 +419,54 @@ __device__ __forceinline__ void soc_case(double t, double a, double& that, doubl
 constexpr int DR_STAGE = NRTO_DR_STAGE;   // chunks of 64 entries a lane holds per sweep
 
 template <int NX, int NU, typename F, int E>
-__device__ __forceinline__ void dr_long_cone(const WaveTask tk, const int32_t* __restrict__ m, F* __restrict__ st,
-                                             const F* __restrict__ bhat, const F* __restrict__ bvec,
-                                             const F* Kf, F* Racc, int T, F r, double al, double ptc_num,
-                                             double sig, double den, double* ca_pt, double* ca_ptt,
-                                             double (&acc)[5]) {
+__device__ __forceinline__ void dr_long_cone(const WaveTask tk, const G<int32_t>* __restrict__ m,
+                                             G<F>* __restrict__ st, const G<F>* __restrict__ bhat,
+                                             const G<F>* __restrict__ bvec, const F* Kf, F* Racc, int T, F r,
+                                             double al, double ptc_num, double sig, double den,
+                                             G<double>* ca_pt, G<double>* ca_ptt, double (&acc)[5]) {
   const int lane = lane_id();
   const int len = tk.len;
   const int k0 = m[CM_K0], boff = m[CM_BOFF];
-  F stv[E], bhv[E], fv[E];
+  // every load of the cone first: s~, b_hat and the block vector of each entry
+  // (a state constraint at t = T stores a zero block T, so the block vector of
+  // every entry exists)
+  F stv[E], bhv[E], bvr[E][NU];
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int le = lane + i * NRTO_WAVE;
     stv[i] = (F)0;
     bhv[i] = (F)0;
+#pragma unroll
+    for (int u = 0; u < NU; ++u) bvr[i][u] = (F)0;
     if (le < len) {
       stv[i] = st[le];
-      bhv[i] = bhat[le];
+      if (le >= 1) {
+        bhv[i] = bhat[le];
+        const G<F>* bv = bvec + (int64_t)(boff + (le - 1) / NX) * NU;
+#pragma unroll
+        for (int u = 0; u < NU; ++u) bvr[i][u] = bv[u];
+      }
     }
   }
   // forward gain GEMM and the norm of the reflected eta
+  F sv[E];
   double sq = 0.0;
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int le = lane + i * NRTO_WAVE;
-    fv[i] = (F)0;
+    sv[i] = (F)0;
     if (le >= 1 && le < len) {
       const int q = le - 1;
       const int blk = q / NX;
       const int x = q - blk * NX;
       const int k = k0 + blk;
+      F f = (F)0;
       if (k < T) {   // the last block of a state constraint at t = T has no gain
-        const F* bv = bvec + (int64_t)(boff + blk) * NU;
-        F f = (F)0;
 #pragma unroll
-        for (int u = 0; u < NU; ++u) f += bv[u] * Kf[(u * T + k) * NX + x];
-        fv[i] = f;
+        for (int u = 0; u < NU; ++u) f += bvr[i][u] * Kf[(u * T + k) * NX + x];
       }
-      const F s = r * fv[i] + bhv[i];
-      const F sr = (F)2 * s - stv[i];
+      sv[i] = r * f + bhv[i];
+      const F sr = (F)2 * sv[i] - stv[i];
       sq += (double)sr * (double)sr;
     }
   }
@@ -472,7 +489,7 @@ __device__ __forceinline__ void dr_long_cone(const WaveTask tk, const int32_t* _
         s = (F)ptc;
         shat = (F)that;
       } else {
-        s = r * fv[i] + bhv[i];
+        s = sv[i];
         const F sr = (F)2 * s - stv[i];
         shat = (F)(scale * (double)sr);
       }
@@ -489,10 +506,9 @@ __device__ __forceinline__ void dr_long_cone(const WaveTask tk, const int32_t* _
         const int x = q - blk * NX;
         const int k = k0 + blk;
         if (k < T) {
-          const F* bv = bvec + (int64_t)(boff + blk) * NU;
           const F d = stn - bhv[i];
 #pragma unroll
-          for (int u = 0; u < NU; ++u) atomicAdd(&Racc[(u * T + k) * NX + x], bv[u] * d);
+          for (int u = 0; u < NU; ++u) atomicAdd(&Racc[(u * T + k) * NX + x], bvr[i][u] * d);
         }
       }
     }
@@ -512,10 +528,11 @@ __device__ __forceinline__ void dr_long_cone(const WaveTask tk, const int32_t* _
 // second reloads the group, recomputes eta, projects, relaxes and accumulates
 // the adjoint); the loads of a group are issued together.
 template <int NX, int NU, typename F, int E>
-__device__ void dr_long_cone_2pass(const WaveTask tk, const int32_t* __restrict__ m, F* __restrict__ st,
-                                   const F* __restrict__ bhat, const F* __restrict__ bvec, const F* Kf, F* Racc,
-                                   int T, F r, double al, double ptc_num, double sig, double den, double* ca_pt,
-                                   double* ca_ptt, double (&acc)[5]) {
+__device__ __forceinline__ void dr_long_cone_2pass(const WaveTask tk, const G<int32_t>* __restrict__ m,
+                                                   G<F>* __restrict__ st, const G<F>* __restrict__ bhat,
+                                                   const G<F>* __restrict__ bvec, const F* Kf, F* Racc, int T, F r,
+                                                   double al, double ptc_num, double sig, double den,
+                                                   G<double>* ca_pt, G<double>* ca_ptt, double (&acc)[5]) {
   const int lane = lane_id();
   const int len = tk.len;
   const int k0 = m[CM_K0], boff = m[CM_BOFF];
@@ -526,15 +543,20 @@ __device__ void dr_long_cone_2pass(const WaveTask tk, const int32_t* __restrict_
     tr0 = (double)((F)2 * (F)ptc - st0);
   }
   for (int base = 0; base < len; base += E * NRTO_WAVE) {
-    F stv[E], bhv[E];
+    F stv[E], bhv[E], bvr[E][NU];
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const int le = base + lane + i * NRTO_WAVE;
       stv[i] = (F)0;
       bhv[i] = (F)0;
+#pragma unroll
+      for (int u = 0; u < NU; ++u) bvr[i][u] = (F)0;
       if (le >= 1 && le < len) {
         stv[i] = st[le];
         bhv[i] = bhat[le];
+        const G<F>* bv = bvec + (int64_t)(boff + (le - 1) / NX) * NU;
+#pragma unroll
+        for (int u = 0; u < NU; ++u) bvr[i][u] = bv[u];
       }
     }
 #pragma unroll
@@ -544,9 +566,8 @@ __device__ void dr_long_cone_2pass(const WaveTask tk, const int32_t* __restrict_
         const int q = le - 1, blk = q / NX, x = q - blk * NX, k = k0 + blk;
         F f = (F)0;
         if (k < T) {
-          const F* bv = bvec + (int64_t)(boff + blk) * NU;
 #pragma unroll
-          for (int u = 0; u < NU; ++u) f += bv[u] * Kf[(u * T + k) * NX + x];
+          for (int u = 0; u < NU; ++u) f += bvr[i][u] * Kf[(u * T + k) * NX + x];
         }
         const F sr = (F)2 * (r * f + bhv[i]) - stv[i];
         sq += (double)sr * (double)sr;
@@ -559,15 +580,22 @@ __device__ void dr_long_cone_2pass(const WaveTask tk, const int32_t* __restrict_
   soc_case(tref, a, that, scale);
   double dsum = 0.0, nsum = 0.0, ssum = 0.0;
   for (int base = 0; base < len; base += E * NRTO_WAVE) {
-    F stv[E], bhv[E];
+    F stv[E], bhv[E], bvr[E][NU];
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const int le = base + lane + i * NRTO_WAVE;
       stv[i] = (F)0;
       bhv[i] = (F)0;
+#pragma unroll
+      for (int u = 0; u < NU; ++u) bvr[i][u] = (F)0;
       if (le < len) {
         stv[i] = st[le];
-        if (le >= 1) bhv[i] = bhat[le];
+        if (le >= 1) {
+          bhv[i] = bhat[le];
+          const G<F>* bv = bvec + (int64_t)(boff + (le - 1) / NX) * NU;
+#pragma unroll
+          for (int u = 0; u < NU; ++u) bvr[i][u] = bv[u];
+        }
       }
     }
 #pragma unroll
@@ -575,20 +603,19 @@ __device__ void dr_long_cone_2pass(const WaveTask tk, const int32_t* __restrict_
       const int le = base + lane + i * NRTO_WAVE;
       if (le < len) {
         F s, shat;
-        int k = 0, x = 0, blk = 0;
+        int k = 0, x = 0;
         if (le == 0) {
           s = (F)ptc;
           shat = (F)that;
         } else {
           const int q = le - 1;
-          blk = q / NX;
+          const int blk = q / NX;
           x = q - blk * NX;
           k = k0 + blk;
           F f = (F)0;
           if (k < T) {
-            const F* bv = bvec + (int64_t)(boff + blk) * NU;
 #pragma unroll
-            for (int u = 0; u < NU; ++u) f += bv[u] * Kf[(u * T + k) * NX + x];
+            for (int u = 0; u < NU; ++u) f += bvr[i][u] * Kf[(u * T + k) * NX + x];
           }
           s = r * f + bhv[i];
           shat = (F)(scale * (double)((F)2 * s - stv[i]));
@@ -601,10 +628,9 @@ __device__ void dr_long_cone_2pass(const WaveTask tk, const int32_t* __restrict_
         nsum += (double)stn * (double)stn;
         ssum += (double)s * (double)s;
         if (le > 0 && k < T) {
-          const F* bv = bvec + (int64_t)(boff + blk) * NU;
           const F d = stn - bhv[i];
 #pragma unroll
-          for (int u = 0; u < NU; ++u) atomicAdd(&Racc[(u * T + k) * NX + x], bv[u] * d);
+          for (int u = 0; u < NU; ++u) atomicAdd(&Racc[(u * T + k) * NX + x], bvr[i][u] * d);
         }
       }
     }
@@ -619,37 +645,92 @@ __device__ void dr_long_cone_2pass(const WaveTask tk, const int32_t* __restrict_
   acc[4] += ssum;
 }
 
+// Arguments of the DR pass, passed by value to a separately compiled function
+// so that its register allocation does not compete with the rest of the solve.
+template <typename F>
+struct DrArgs {
+  const WaveTask* tasks;
+  const uint64_t* tmask;
+  const int32_t* cm;
+  double* ca;          // per-cone columns, column stride cstride
+  int64_t cstride;
+  F* st;
+  const F* bhat;
+  const F* bvec;
+  const F* Kf;
+  F* Racc;
+  double* wscr;
+  int* ctr;
+  int64_t lds_ctr_off;   // byte offset of ctr in the dynamic LDS
+  int T, ntask;
+  double r, al, sigma_chi, rho, sig;
+};
+
+struct Acc5 {
+  double v[5];
+};
+
+// A function compiled on its own only sees generic pointers in its arguments:
+// the DR pass re-derives their address spaces (G<T>: global memory; as_lds: the
+// workgroup's dynamic LDS) so that it issues global and LDS instructions
+// instead of flat ones.
+template <typename T>
+__device__ __forceinline__ T* as_lds(const void* p, const char* base) {
+  return (T*)(nrto_dyn_smem + ((const char*)p - base));
+}
+
 template <int NX, int NU, typename F>
-__device__ void dr_pass(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o, double rho, double sig,
-                        double (&acc)[5]) {
-  const int T = I.T;
+__device__ __noinline__ Acc5 dr_pass_impl(DrArgs<F> g) {
+  {
+    const char* base = (const char*)g.ctr - g.lds_ctr_off;
+    g.Kf = as_lds<F>(g.Kf, base);
+    g.Racc = as_lds<F>(g.Racc, base);
+    g.wscr = as_lds<double>(g.wscr, base);
+    g.ctr = as_lds<int>(g.ctr, base);
+  }
+  const G<WaveTask>* tasks = (const G<WaveTask>*)g.tasks;
+  const G<uint64_t>* tmask = (const G<uint64_t>*)g.tmask;
+  const G<int32_t>* cmeta = (const G<int32_t>*)g.cm;
+  G<double>* ca = (G<double>*)g.ca;
+  G<F>* gst = (G<F>*)g.st;
+  const G<F>* gbhat = (const G<F>*)g.bhat;
+  const G<F>* gbvec = (const G<F>*)g.bvec;
+  Acc5 out;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const int T = g.T;
   const int lane = lane_id();
-  const F r = (F)I.r;
-  const double al = o.alpha;
-  const double den = rho + o.sigma_chi + sig;
-  double* ws = S.wscr + wave_id() * 128;
-  for (int t = next_task(S.ctr); t < I.ntask; t = next_task(S.ctr)) {
-    const WaveTask tk = I.tasks[t];
+  const F r = (F)g.r;
+  const double al = g.al;
+  const double den = g.rho + g.sigma_chi + g.sig;
+  const double rho = g.rho, sig = g.sig;
+  double* ws = g.wscr + wave_id() * 128;
+  auto C = [&](int col, int j) -> G<double>& { return ca[(int64_t)col * g.cstride + j]; };
+  for (int t = next_task(g.ctr); t < g.ntask; t = next_task(g.ctr)) {
+    WaveTask tk;
+    tk.cone = tasks[t].cone;
+    tk.ncone = tasks[t].ncone;
+    tk.ebeg = tasks[t].ebeg;
+    tk.len = tasks[t].len;
     if (tk.ncone == 1 && tk.len > NRTO_WAVE) {
       const int c = tk.cone;
-      const int32_t* m = I.cm + c * CM_N;
-      const double ptc_num = o.sigma_chi * I.C(CA_PTT, c) + rho * I.C(CA_P, c) + I.C(CA_LAM, c);
-      F* st = I.st + tk.ebeg;
-      const F* bh = I.bhat + tk.ebeg;
-      double* cpt = &I.C(CA_PT, c);
-      double* cptt = &I.C(CA_PTT, c);
+      const G<int32_t>* m = cmeta + c * CM_N;
+      const double ptc_num = g.sigma_chi * C(CA_PTT, c) + rho * C(CA_P, c) + C(CA_LAM, c);
+      G<F>* st = gst + tk.ebeg;
+      const G<F>* bh = gbhat + tk.ebeg;
+      G<double>* cpt = &C(CA_PT, c);
+      G<double>* cptt = &C(CA_PTT, c);
       if (tk.len <= 2 * NRTO_WAVE)
-        dr_long_cone<NX, NU, F, 2>(tk, m, st, bh, I.bvec, S.Kf, S.Racc, T, r, al, ptc_num, sig, den, cpt, cptt, acc);
+        dr_long_cone<NX, NU, F, 2>(tk, m, st, bh, gbvec, g.Kf, g.Racc, T, r, al, ptc_num, sig, den, cpt, cptt, acc);
       else if (tk.len <= DR_STAGE * NRTO_WAVE)
-        dr_long_cone<NX, NU, F, DR_STAGE>(tk, m, st, bh, I.bvec, S.Kf, S.Racc, T, r, al, ptc_num, sig, den, cpt,
+        dr_long_cone<NX, NU, F, DR_STAGE>(tk, m, st, bh, gbvec, g.Kf, g.Racc, T, r, al, ptc_num, sig, den, cpt,
                                           cptt, acc);
       else
-        dr_long_cone_2pass<NX, NU, F, DR_STAGE>(tk, m, st, bh, I.bvec, S.Kf, S.Racc, T, r, al, ptc_num, sig, den,
+        dr_long_cone_2pass<NX, NU, F, DR_STAGE>(tk, m, st, bh, gbvec, g.Kf, g.Racc, T, r, al, ptc_num, sig, den,
                                                 cpt, cptt, acc);
     } else {
       // packed short cones: one entry per lane; each lane reads its cone's
       // metadata and its block vector once
-      const uint64_t mask = I.tmask[t];
+      const uint64_t mask = tmask[t];
       const int l = lane;
       const bool valid = l < tk.len;
       const uint64_t pre = mask & ((l == 63) ? ~0ull : ((2ull << l) - 1ull));
@@ -668,25 +749,25 @@ __device__ void dr_pass(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o
       bool has_gain = false;
       if (valid) {
         const int64_t e = tk.ebeg + l;
-        stv = I.st[e];
+        stv = gst[e];
         if (le == 0) {
-          ptc = (o.sigma_chi * I.C(CA_PTT, c) + rho * I.C(CA_P, c) + I.C(CA_LAM, c) + sig * (double)stv) / den;
+          ptc = (g.sigma_chi * C(CA_PTT, c) + rho * C(CA_P, c) + C(CA_LAM, c) + sig * (double)stv) / den;
           s = (F)ptc;
           ws[64 + cl] = (double)((F)2 * s - stv);
         } else {
-          const int32_t* m = I.cm + c * CM_N;
+          const G<int32_t>* m = cmeta + c * CM_N;
           const int q = le - 1, blk = q / NX;
           x = q - blk * NX;
           k = m[CM_K0] + blk;
-          bh = I.bhat[e];
+          bh = gbhat[e];
           F f = (F)0;
           if (k < T) {
             has_gain = true;
-            const F* bv = I.bvec + (int64_t)(m[CM_BOFF] + blk) * NU;
+            const G<F>* bv = gbvec + (int64_t)(m[CM_BOFF] + blk) * NU;
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
               bvr[u] = bv[u];
-              f += bvr[u] * S.Kf[(u * T + k) * NX + x];
+              f += bvr[u] * g.Kf[(u * T + k) * NX + x];
             }
           }
           s = r * f + bh;
@@ -705,27 +786,59 @@ __device__ void dr_pass(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o
         const F shat = (le == 0) ? (F)that : (F)(scale * (double)sr);
         const F diff = shat - s;
         const F stn = stv + (F)al * diff;
-        I.st[e] = stn;
+        gst[e] = stn;
         const double dd = al * (double)diff;
         acc[0] += dd * dd;
         acc[1] += (double)stn * (double)stn;
         acc[4] += (double)s * (double)s;
         if (le == 0) {
-          I.C(CA_PT, c) = ptc;
-          const double pt0 = I.C(CA_PTT, c);
-          I.C(CA_PTT, c) = pt0 + al * (ptc - pt0);
+          C(CA_PT, c) = ptc;
+          const double pt0 = C(CA_PTT, c);
+          C(CA_PTT, c) = pt0 + al * (ptc - pt0);
         } else if (has_gain) {
           const F d = stn - bh;
 #pragma unroll
           for (int u = 0; u < NU; ++u) {
             const F cu = bvr[u] * d;
-            if (cu != (F)0) atomicAdd(&S.Racc[(u * T + k) * NX + x], cu);
+            if (cu != (F)0) atomicAdd(&g.Racc[(u * T + k) * NX + x], cu);
           }
         }
       }
       wave_sync();
     }
   }
+#pragma unroll
+  for (int i = 0; i < 5; ++i) out.v[i] = acc[i];
+  return out;
+}
+
+template <int NX, int NU, typename F>
+__device__ __forceinline__ void dr_pass(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o, double rho,
+                                        double sig, double (&acc)[5]) {
+  DrArgs<F> g;
+  g.tasks = I.tasks;
+  g.tmask = I.tmask;
+  g.cm = I.cm;
+  g.ca = I.ca;
+  g.cstride = I.cstride;
+  g.st = I.st;
+  g.bhat = I.bhat;
+  g.bvec = I.bvec;
+  g.Kf = S.Kf;
+  g.Racc = S.Racc;
+  g.wscr = S.wscr;
+  g.ctr = S.ctr;
+  g.lds_ctr_off = (int64_t)((const char*)S.ctr - (const char*)nrto_dyn_smem);
+  g.T = I.T;
+  g.ntask = I.ntask;
+  g.r = I.r;
+  g.al = o.alpha;
+  g.sigma_chi = o.sigma_chi;
+  g.rho = rho;
+  g.sig = sig;
+  const Acc5 a = dr_pass_impl<NX, NU, F>(g);
+#pragma unroll
+  for (int i = 0; i < 5; ++i) acc[i] += a.v[i];
 }
 
 // R pass: Racc = sum_j b_jk (s~_eta - b_hat)' from the current DR state.
@@ -1984,7 +2097,7 @@ template <int NX, int NU, typename F>
 __global__ void __launch_bounds__(NRTO_SOLVER_MAX_THREADS)
 warm_kernel(DevPtrs g, SolveOpts o, const int32_t* order, int n, const float* pred, int64_t ld, int test,
             int32_t* accepted, double* res) {
-  extern __shared__ __align__(16) char smem[];
+  char* smem = nrto_dyn_smem;
   const int ii = order[blockIdx.x];
   Inst<NX, NU, F> I = make_inst<NX, NU, F>(g, ii);
   const int W = blockDim.x / NRTO_WAVE;
@@ -2058,7 +2171,7 @@ hipError_t launch_warm(const DevPtrs& g, const SolveOpts& o, int nx, const int32
 
 template <int NX, int NU, typename F, int METHOD>
 __global__ void __launch_bounds__(NRTO_SOLVER_MAX_THREADS) solve_kernel(DevPtrs g, SolveOpts o, const int32_t* order, int n) {
-  extern __shared__ __align__(16) char smem[];
+  char* smem = nrto_dyn_smem;
   const int ii = order[blockIdx.x];
   solve_instance<NX, NU, F, METHOD>(g, o, ii, smem);
 }

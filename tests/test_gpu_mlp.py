@@ -1,7 +1,8 @@
 """GPU checks of the warm-start network kernels: the BF16 matrix-core GEMM
 (fragment layouts, ragged edges, strided operands) against an exact product
-of the bf16-rounded inputs, and the network's forward pass and gradients
-against the FP64 reference MLP on the same parameters."""
+of the bf16-rounded inputs, the network's forward pass and gradients against
+the FP64 reference MLP on the same parameters (with and without its bfloat16
+operand rounding), and the Adam kernel against the reference Adam."""
 import numpy as np
 import pytest
 
@@ -59,27 +60,64 @@ def _net_case(torch, widths, B):
     return net, X, T
 
 
-def test_forward_and_gradients_match_fp64_reference():
+@pytest.mark.parametrize("widths,B", [([64, 256, 256, 256, 256, 1400], 64), ([64, 256, 256, 256, 256, 3800], 32)])
+def test_forward_and_gradients_match_reference(widths, B):
+    """Against the FP64 reference with the GEMM operands rounded to bfloat16 as
+    the matrix cores see them (1e-3 relative), and against the exact FP64
+    reference (bf16 operand rounding only, 2e-2)."""
     torch = _torch()
-    widths = [64, 256, 256, 256, 256, 3800]
-    net, X, T = _net_case(torch, widths, 64)
+    net, X, T = _net_case(torch, widths, B)
     params = [[W.astype(np.float64), b.astype(np.float64)] for W, b in net.get_params()]
     for l in range(len(params)):           # non-zero biases exercise the bias paths
         params[l][1] = 0.05 * (2 * synth.uniform(50 + l, params[l][1].size) - 1)
     net.set_params(params)
+    params = [[W.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64)]
+              for W, b in params]
     Xd = torch.from_numpy(X).cuda()
     Td = torch.from_numpy(T).cuda()
+    X64, T64 = X.astype(np.float64), T.astype(np.float64)
     Y = net.infer(Xd).cpu().numpy().astype(np.float64)
-    Yr, _, _ = mlp.forward(params, X.astype(np.float64))
+    Yq, _, _ = mlp.forward(params, X64, rnd=mlp.round_bf16)
+    Yr, _, _ = mlp.forward(params, X64)
+    assert np.linalg.norm(Y - Yq) <= 1e-3 * np.linalg.norm(Yq)
     assert np.linalg.norm(Y - Yr) <= 2e-2 * np.linalg.norm(Yr)
     grads, loss = net.gradients(Xd, Td)
-    lr, gr = mlp.loss_and_grads(params, X.astype(np.float64), T.astype(np.float64))
+    lq, gq = mlp.loss_and_grads(params, X64, T64, rnd=mlp.round_bf16)
+    lr, gr = mlp.loss_and_grads(params, X64, T64)
+    assert abs(loss - lq) <= 1e-3 * lq
     assert abs(loss - lr) <= 2e-2 * lr
     for l in range(len(params)):
         for i in range(2):
             g = grads[l][i].astype(np.float64)
-            r = gr[l][i]
-            assert np.linalg.norm(g - r) <= 3e-2 * np.linalg.norm(r) + 1e-12, (l, i)
+            assert np.linalg.norm(g - gq[l][i]) <= 1e-3 * np.linalg.norm(gq[l][i]) + 1e-12, (l, i)
+            assert np.linalg.norm(g - gr[l][i]) <= 3e-2 * np.linalg.norm(gr[l][i]) + 1e-12, (l, i)
+
+
+def test_adam_steps_match_reference_elementwise():
+    """Two Adam steps of the device optimizer against the reference Adam applied
+    to the same (device) gradients from the same parameters."""
+    torch = _torch()
+    widths = [64, 256, 256, 1400]
+    net, X, T = _net_case(torch, widths, 64)
+    Xd = torch.from_numpy(X).cuda()
+    Td = torch.from_numpy(T).cuda()
+    ref = [[W.astype(np.float64), b.astype(np.float64)] for W, b in net.get_params()]
+    # the device runs Adam with the float32 values of its constants (1 - 0.999 in
+    # float32 is off by 1.3e-5 relative); the reference takes the same values
+    f32 = lambda v: float(np.float32(v))
+    lr = f32(1e-3)
+    opt = mlp.Adam(ref, lr=lr, b1=f32(0.9), b2=f32(0.999), eps=f32(1e-8))
+    for step in range(2):
+        g, _ = net.gradients(Xd, Td)
+        net.train_step(Xd, Td, 1e-3, want_loss=False)
+        opt.step(ref, [[gw.astype(np.float64), gb.astype(np.float64)] for gw, gb in g])
+        got = net.get_params()
+        for l in range(len(ref)):
+            for i in range(2):
+                a = got[l][i].astype(np.float64)
+                d = np.abs(a - ref[l][i])
+                assert np.all(d <= 1e-6 * np.abs(ref[l][i]) + 1e-6 * lr), (step, l, i, float(d.max()))
+        ref = [[W.astype(np.float64), b.astype(np.float64)] for W, b in got]   # continue from the device's values
 
 
 def test_training_reduces_loss():

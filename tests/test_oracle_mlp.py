@@ -49,3 +49,36 @@ def test_adam_first_step_is_signed_lr():
     opt.step(params, grads)
     assert np.allclose(params[0][0], [[1.0 - 0.01 * 0.3 / (0.3 + 1e-8), -2.0 + 0.01 * 0.4 / (0.4 + 1e-8)]])
     assert np.allclose(params[0][1], [0.5 - 0.01 * 2.0 / (2.0 + 1e-8)])
+
+
+def test_round_bf16_ties_to_even_and_nearest():
+    r = mlp.round_bf16
+    exact = np.array([1.0, 1.5, -2.0, 3.0, 0.0, 2.0 ** -20, -(1 + 2.0 ** -7)])
+    assert np.array_equal(r(exact), exact)
+    assert r(np.array([1 + 2.0 ** -8]))[0] == 1.0                       # tie -> even (1.0)
+    assert r(np.array([1 + 3 * 2.0 ** -8]))[0] == 1 + 2.0 ** -6         # tie -> even (1 + 2^-6)
+    assert r(np.array([1 + 2.0 ** -8 + 2.0 ** -20]))[0] == 1 + 2.0 ** -7
+    assert r(np.array([-(1 + 2.0 ** -8 + 2.0 ** -20)]))[0] == -(1 + 2.0 ** -7)
+    # brute force: the result has an 8-bit significand and no bf16 neighbour is closer
+    x = (2 * synth.uniform(31, 2000) - 1) * 10.0 ** (8 * synth.uniform(32, 2000) - 4)
+    y = r(x)
+    bits = y.astype(np.float32).view(np.uint32)
+    assert np.all(bits & 0xFFFF == 0)
+    up = (bits.astype(np.uint64) + 0x10000).astype(np.uint32).view(np.float32).astype(np.float64)
+    dn = (bits.astype(np.uint64) - 0x10000).astype(np.uint32).view(np.float32).astype(np.float64)
+    xf = x.astype(np.float32).astype(np.float64)
+    assert np.all(np.abs(xf - y) <= np.abs(xf - up)) and np.all(np.abs(xf - y) <= np.abs(xf - dn))
+
+
+def test_bf16_operand_gradients_stay_close_to_exact():
+    widths = [16, 32, 32, 8]
+    params = mlp.init_params(widths, 5)
+    X = 2 * synth.uniform(33, 40 * 16).reshape(40, 16) - 1
+    Tg = synth.uniform(34, 40 * 8).reshape(40, 8)
+    l0, g0 = mlp.loss_and_grads(params, X, Tg)
+    l1, g1 = mlp.loss_and_grads(params, X, Tg, rnd=mlp.round_bf16)
+    assert l1 != l0 and abs(l1 - l0) <= 2e-2 * l0
+    for l in range(len(params)):
+        for i in range(2):
+            a, b = g1[l][i], g0[l][i]
+            assert np.linalg.norm(a - b) <= 3e-2 * np.linalg.norm(b)
