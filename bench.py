@@ -156,7 +156,9 @@ def progress(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def _leg_summary(reports, solve_ms, ms, steps, bpp):
+def _leg_summary(reports, phases, solve_ms, ms, steps, bpp):
+    """reports: per-step results (solve or successive-linearisation step
+    reports); phases: the solve reports of the same steps (device timers)."""
     conv = np.array([[r.kkt <= 1e-4 for r in rep] for rep in reports])
     inner = np.array([[r.inner_iters for r in rep] for rep in reports], dtype=np.float64)
     admm = np.array([[r.admm_iters for r in rep] for rep in reports], dtype=np.float64)
@@ -166,10 +168,10 @@ def _leg_summary(reports, solve_ms, ms, steps, bpp):
         "ms_per_step": ms, "steps": steps, "solves": int(conv.size), "converged": int(conv.sum()),
         "admm_iters_mean": float(admm.mean()), "dr_iters_mean": float(inner.mean()),
         "solve_ms_per_step": float(np.mean(solve_ms)),
-        "workgroup_us_mean": {k: float(np.mean([getattr(r, k) for rep in reports for r in rep]))
+        "workgroup_us_mean": {k: float(np.mean([getattr(r, k) for rep in phases for r in rep]))
                               for k in ("t_dr_us", "t_qp_us", "t_kkt_us", "t_total_us")},
-        "riccati_per_admm": float(sum(r.qp_newton for rep in reports for r in rep) /
-                                  max(1, sum(r.admm_iters for rep in reports for r in rep))),
+        "riccati_per_admm": float(sum(r.qp_newton for rep in phases for r in rep) /
+                                  max(1, sum(r.admm_iters for rep in phases for r in rep))),
         "_alg_bytes": alg_bytes, "_solve_ms": np.asarray(solve_ms),
     }
 
@@ -298,13 +300,14 @@ def main():
                 progress(f"{mode} warmup step {w + 1}/{warmup} done")
         torch.cuda.synchronize()
         start, stop = ev(), ev()
-        reports = []
+        reports, phases = [], []
         with torch.cuda.stream(stream):
             torch.cuda.synchronize()
             start.record(stream)
             for k in range(steps):
                 step(k)
-                reports.append(ctx.scp_accept() if advance else ctx.reports())
+                phases.append(ctx.reports())
+                reports.append(ctx.scp_accept() if advance else phases[-1])
                 progress(f"{mode} timed step {k + 1}/{steps} done")
             stop.record(stream)
         stop.synchronize()
@@ -313,7 +316,7 @@ def main():
         solve_ms = [a.elapsed_time(b) for a, b in solve_ev]
         if mode == "learned":
             mlp_ms = [a.elapsed_time(b) for a, b in infer_ev]
-        s = _leg_summary(reports, solve_ms, ms, steps, bpp)
+        s = _leg_summary(reports, phases, solve_ms, ms, steps, bpp)
         s["fallback_rate"] = float(np.mean(fallback)) if fallback else None
         s["_mlp_ms"] = mlp_ms
         return s

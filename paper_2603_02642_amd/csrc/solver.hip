@@ -20,10 +20,6 @@ namespace nrto {
 
 constexpr int EMAX = 16;
 
-// An object in global memory (device allocations).
-template <typename T>
-using G = __attribute__((address_space(1))) T;
-
 // The workgroup's dynamic LDS (one instance's gains, adjoint accumulator,
 // factors, reduction slots and (du, p) scratch).
 extern __shared__ __align__(16) char nrto_dyn_smem[];
@@ -42,23 +38,43 @@ __device__ __forceinline__ double atomic_load_agent(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Objects in global memory (device allocations) and in the workgroup's LDS.
+// The pointers of an instance and of its LDS carve-up carry their address
+// space in their type, so that functions the compiler keeps out of line
+// still issue global and LDS instructions rather than flat ones (a flat load
+// counts against both wait counters and so serialises LDS reads behind
+// outstanding global loads).
+// (The host pass of the compiler has no such address spaces; there the aliases
+// are the plain types.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using G = __attribute__((address_space(1))) T;
+template <typename T>
+using L = __attribute__((address_space(3))) T;
+#else
+template <typename T>
+using G = T;
+template <typename T>
+using L = T;
+#endif
+
 // Shared-memory carve-up for one instance workgroup.
 template <typename F>
 struct Smem {
-  F* Kf;        // NU*T*NX, u-major: Kf[(u*T + k)*NX + x]
-  F* Racc;      // NU*T*NX, same layout
-  double* Gl;   // T*NU*NU Cholesky factors
-  double* red;  // 128: [0, 64) block reductions, [64, 128) broadcast scalars
-  double* wscr; // W*128: per-wave cone sums / broadcast
-  double* qp;   // wave-0 QP scratch
-  int* ctr;     // 4 ints
+  L<F>* Kf;        // NU*T*NX, u-major: Kf[(u*T + k)*NX + x]
+  L<F>* Racc;      // NU*T*NX, same layout
+  L<double>* Gl;   // T*NU*NU Cholesky factors
+  L<double>* red;  // 128: [0, 64) block reductions, [64, 128) broadcast scalars
+  L<double>* wscr; // W*128: per-wave cone sums / broadcast
+  L<double>* qp;   // wave-0 QP scratch
+  L<int>* ctr;     // 4 ints
 };
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
 __host__ __device__ inline size_t qp_scratch_doubles(int nx, int nu) {
   return 2 * nx * nx + nx + nx * nu + 2 * nu * nu + nu * nx + nu + 2 * nx + 64 +
-         2 * (nx * nx + nx * nu) + nu * (nx + 1) + nx * nx + nu * nu + nx;
+         2 * (nx * nx + nx * nu + nu * (nx + 1)) + nu * (nx + 1) + nx * nx + nu * nu + nx + 160;
 }
 
 __host__ __device__ inline size_t smem_bytes(int T, int nx, int nu, int fbytes, int W) {
@@ -74,16 +90,16 @@ __host__ __device__ inline size_t smem_bytes(int T, int nx, int nu, int fbytes, 
 }
 
 template <typename F>
-__device__ Smem<F> carve(char* base, int T, int nx, int nu, int W) {
+__device__ Smem<F> carve(L<char>* base, int T, int nx, int nu, int W) {
   Smem<F> m;
   size_t o = 0;
-  m.Kf = (F*)(base + o); o += align16((size_t)nu * T * nx * sizeof(F));
-  m.Racc = (F*)(base + o); o += align16((size_t)nu * T * nx * sizeof(F));
-  m.Gl = (double*)(base + o); o += align16((size_t)T * nu * nu * 8);
-  m.red = (double*)(base + o); o += align16(128 * 8);
-  m.wscr = (double*)(base + o); o += align16((size_t)W * 128 * 8);
-  m.qp = (double*)(base + o); o += align16(qp_scratch_doubles(nx, nu) * 8);
-  m.ctr = (int*)(base + o);
+  m.Kf = (L<F>*)(base + o); o += align16((size_t)nu * T * nx * sizeof(F));
+  m.Racc = (L<F>*)(base + o); o += align16((size_t)nu * T * nx * sizeof(F));
+  m.Gl = (L<double>*)(base + o); o += align16((size_t)T * nu * nu * 8);
+  m.red = (L<double>*)(base + o); o += align16(128 * 8);
+  m.wscr = (L<double>*)(base + o); o += align16((size_t)W * 128 * 8);
+  m.qp = (L<double>*)(base + o); o += align16(qp_scratch_doubles(nx, nu) * 8);
+  m.ctr = (L<int>*)(base + o);
   return m;
 }
 
@@ -171,26 +187,26 @@ template <int NX, int NU, typename F>
 struct Inst {
   int T, ng, nent, ntask;
   double r, r_trust;
-  const int32_t* cm;
-  double* ca;        // carr + cone0; column stride = ncones
+  const G<int32_t>* cm;
+  G<double>* ca;        // carr + cone0; column stride = ncones
   int64_t cstride;
-  const double* W;
-  const F* bhat;
-  const F* bvec;
-  F* st;
-  F* nuv;
-  const double *A, *B, *xhat, *uhat;
-  double *dx, *du, *dx2, *du2, *K, *Kt, *kscr, *ric;
-  const double *Q, *Ru, *RK2, *xg;
-  const int32_t* tls;  // state cones by time: [tls[t], tls[t+1])
-  const int32_t* tlc;  // control cones by step: [tlc[k], tlc[k+1])
-  const WaveTask* tasks;
-  const uint64_t* tmask;
-  double* mu;
-  double* iscr;
-  int32_t* flags;
+  const G<double>* W;
+  const G<F>* bhat;
+  const G<F>* bvec;
+  G<F>* st;
+  G<F>* nuv;
+  const G<double> *A, *B, *xhat, *uhat;
+  G<double> *dx, *du, *dx2, *du2, *K, *Kt, *kscr, *ric;
+  const G<double> *Q, *Ru, *RK2, *xg;
+  const G<int32_t>* tls;  // state cones by time: [tls[t], tls[t+1])
+  const G<int32_t>* tlc;  // control cones by step: [tlc[k], tlc[k+1])
+  const G<WaveTask>* tasks;
+  const G<uint64_t>* tmask;
+  G<double>* mu;
+  G<double>* iscr;
+  G<int32_t>* flags;
 
-  __device__ double& C(int a, int j) const { return ca[(int64_t)a * cstride + j]; }
+  __device__ G<double>& C(int a, int j) const { return ca[(int64_t)a * cstride + j]; }
 };
 
 template <int NX, int NU, typename F>
@@ -203,39 +219,39 @@ __device__ Inst<NX, NU, F> make_inst(const DevPtrs& g, int ii) {
   I.ntask = d.ntask;
   I.r = d.radius;
   I.r_trust = d.r_trust;
-  I.cm = g.cmeta + d.cone0 * CM_N;
-  I.ca = g.carr + d.cone0;
+  I.cm = (const G<int32_t>*)(g.cmeta + d.cone0 * CM_N);
+  I.ca = (G<double>*)(g.carr + d.cone0);
   I.cstride = g.ncones;
-  I.W = g.w + d.oW;
-  I.bhat = bhat_ptr<F>(g) + d.ent0;
-  I.bvec = bvec_ptr<F>(g) + d.bv0;
-  I.st = (F*)g.st + d.ent0;
-  I.nuv = (F*)g.nu + d.ent0;
-  I.A = g.A + d.oA;
-  I.B = g.B + d.oB;
-  I.xhat = g.xhat + d.oX;
-  I.uhat = g.uhat + d.oU;
-  I.dx = g.dx + d.oX;
-  I.du = g.du + d.oU;
-  I.dx2 = g.dx2 + d.oX;
-  I.du2 = g.du2 + d.oU;
-  I.K = g.K + d.oK;
-  I.Kt = g.Kt + d.oK;
-  I.kscr = g.kscr + d.oK;
-  I.ric = g.ric + d.oR;
+  I.W = (const G<double>*)(g.w + d.oW);
+  I.bhat = (const G<F>*)(bhat_ptr<F>(g) + d.ent0);
+  I.bvec = (const G<F>*)(bvec_ptr<F>(g) + d.bv0);
+  I.st = (G<F>*)((F*)g.st + d.ent0);
+  I.nuv = (G<F>*)((F*)g.nu + d.ent0);
+  I.A = (const G<double>*)(g.A + d.oA);
+  I.B = (const G<double>*)(g.B + d.oB);
+  I.xhat = (const G<double>*)(g.xhat + d.oX);
+  I.uhat = (const G<double>*)(g.uhat + d.oU);
+  I.dx = (G<double>*)(g.dx + d.oX);
+  I.du = (G<double>*)(g.du + d.oU);
+  I.dx2 = (G<double>*)(g.dx2 + d.oX);
+  I.du2 = (G<double>*)(g.du2 + d.oU);
+  I.K = (G<double>*)(g.K + d.oK);
+  I.Kt = (G<double>*)(g.Kt + d.oK);
+  I.kscr = (G<double>*)(g.kscr + d.oK);
+  I.ric = (G<double>*)(g.ric + d.oR);
   const double* prm = g.prm + d.oP;
   ParamOffsets po = param_offsets(NX, NU, d.n_obs);
-  I.Q = prm + po.Q;
-  I.Ru = prm + po.Ru;
-  I.RK2 = prm + po.RK2;
-  I.xg = prm + po.xg;
-  I.tls = g.tl + d.oTL;
+  I.Q = (const G<double>*)(prm + po.Q);
+  I.Ru = (const G<double>*)(prm + po.Ru);
+  I.RK2 = (const G<double>*)(prm + po.RK2);
+  I.xg = (const G<double>*)(prm + po.xg);
+  I.tls = (const G<int32_t>*)(g.tl + d.oTL);
   I.tlc = I.tls + (d.T + 2);
-  I.tasks = g.tasks + d.task0;
-  I.tmask = g.tmask + d.task0;
-  I.mu = g.mu + ii;
-  I.iscr = g.iscr + (int64_t)ii * ISCR_N;
-  I.flags = g.flags + (int64_t)ii * 4;
+  I.tasks = (const G<WaveTask>*)(g.tasks + d.task0);
+  I.tmask = (const G<uint64_t>*)(g.tmask + d.task0);
+  I.mu = (G<double>*)(g.mu + ii);
+  I.iscr = (G<double>*)(g.iscr + (int64_t)ii * ISCR_N);
+  I.flags = (G<int32_t>*)(g.flags + (int64_t)ii * 4);
   return I;
 }
 
@@ -1008,14 +1024,16 @@ __device__ void fa_commit(const Inst<NX, NU, F>& I, Smem<F>& S) {
 // (du, p) block on wave 0.
 template <int NX, int NU>
 struct QPScratch {
-  double *V, *v, *PA, *PB, *Huu, *Hux, *hu, *L, *tmp, *red;
-  double* AB[2];   // double buffer of one stage's A (NX*NX) and B (NX*NU)
-  double* G;       // gains of the current stage, NU*(NX+1)
-  double *Qs, *Rs, *xg;   // LDS copies of Q, Ru, the goal state
+  L<double> *V, *v, *PA, *PB, *Huu, *Hux, *hu, *Lc, *tmp, *red;   // Lc: Cholesky factor of Huu
+  L<double>* AB[2];   // double buffer of one stage's data: A (NX*NX), B (NX*NU), then x_k, u_k
+                   // (backward pass) or the gains G_k (forward rollout)
+  L<double>* G;       // gains of the current stage, NU*(NX+1)
+  L<double> *Qs, *Rs, *xg;   // LDS copies of Q, Ru, the goal state
+  L<double>* act;     // active state cones of a stage: 64 int indices, 64 betas, 64 gradient values
 };
 
 template <int NX, int NU>
-__device__ QPScratch<NX, NU> qp_carve(double* q) {
+__device__ QPScratch<NX, NU> qp_carve(L<double>* q) {
   QPScratch<NX, NU> s;
   s.V = q; q += NX * NX;
   s.v = q; q += NX;
@@ -1024,79 +1042,155 @@ __device__ QPScratch<NX, NU> qp_carve(double* q) {
   s.Huu = q; q += NU * NU;
   s.Hux = q; q += NU * NX;
   s.hu = q; q += NU;
-  s.L = q; q += NU * NU;
+  s.Lc = q; q += NU * NU;
   s.tmp = q; q += 2 * NX;
   s.red = q; q += 64;
-  s.AB[0] = q; q += NX * NX + NX * NU;
-  s.AB[1] = q; q += NX * NX + NX * NU;
+  s.AB[0] = q; q += NX * NX + NX * NU + NU * (NX + 1);
+  s.AB[1] = q; q += NX * NX + NX * NU + NU * (NX + 1);
   s.G = q; q += NU * (NX + 1);
   s.Qs = q; q += NX * NX;
   s.Rs = q; q += NU * NU;
-  s.xg = q;
+  s.xg = q; q += NX;
+  s.act = q;
   return s;
 }
 
-// Active-set flags of one stage, loaded a stage ahead: lane l holds the flag of
-// state cone tls[t] + l and of control cone tlc[k] + l (cones beyond the first 64
-// of a stage are read directly when used).
+// Active-set flags of one stage, loaded a stage ahead: lane l holds the flag and
+// beta of state cone tls[t] + l, and the flag, beta, input index and sign of
+// control cone tlc[k] + l (cones beyond the first 64 of a stage are read
+// directly when used).
 struct StageFlags {
   int s0, s1, c0, c1;
   bool sf, cf;
+  double sbeta, cbs;   // state beta; control beta times the bound's sign
+  int ccidx;
   template <class InstT>
   __device__ void load(const InstT& I, int t, int k) {
     s0 = I.tls[t];
     s1 = I.tls[t + 1];
     const int l = lane_id();
-    sf = (s0 + l < s1) && I.C(CA_ACT, s0 + l) != 0.0;
+    sf = false;
+    sbeta = 0.0;
+    if (s0 + l < s1) {
+      sf = I.C(CA_ACT, s0 + l) != 0.0;
+      sbeta = I.C(CA_BETA, s0 + l);
+    }
+    cf = false;
+    cbs = 0.0;
+    ccidx = 0;
     if (k >= 0) {
       c0 = I.tlc[k];
       c1 = I.tlc[k + 1];
-      cf = (c0 + l < c1) && I.C(CA_ACT, c0 + l) != 0.0;
+      if (c0 + l < c1) {
+        const int c = c0 + l;
+        cf = I.C(CA_ACT, c) != 0.0;
+        ccidx = I.cm[c * CM_N + CM_CIDX];
+        cbs = I.C(CA_BETA, c) * (double)I.cm[c * CM_N + CM_CSIGN];
+      }
     } else {
       c0 = c1 = 0;
-      cf = false;
     }
   }
 };
 
 // Add the active state-constraint terms of time t to (V, v): rho w w', rho beta w.
+// The active cones of a stage are compacted into an LDS list and their
+// gradient rows gathered in batches of 64 / NX (one load round trip per batch)
+// into a 64-double LDS buffer.
 template <int NX, int NU, typename F>
 __device__ void add_state_terms(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, const StageFlags& fl, double rho) {
   const int lane = lane_id();
-  uint64_t mask = __ballot(fl.sf);
+  constexpr int PERB = NRTO_WAVE / NX;
+  int* act_c = (int*)q.act;
+  double* act_b = q.act + 32;
+  double* wb = q.act + 96;
   for (int base = fl.s0; base < fl.s1; base += NRTO_WAVE) {
-    if (base > fl.s0) mask = __ballot((base + lane < fl.s1) && I.C(CA_ACT, base + lane) != 0.0);
-    while (mask) {
-      const int bit = __ffsll((unsigned long long)mask) - 1;
-      mask &= mask - 1;
-      const int c = base + bit;
-      const double* w = I.W + (int64_t)c * NX;
-      const double be = I.C(CA_BETA, c);
-      if (lane < NX) q.tmp[lane] = w[lane];
+    bool f;
+    double bl;
+    if (base == fl.s0) {
+      f = fl.sf;
+      bl = fl.sbeta;
+    } else {
+      f = (base + lane < fl.s1) && I.C(CA_ACT, base + lane) != 0.0;
+      bl = f ? I.C(CA_BETA, base + lane) : 0.0;
+    }
+    const uint64_t mask = __ballot(f);
+    const int nact = __popcll(mask);
+    if (nact == 0) continue;
+    const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+    if (f) {
+      act_c[rank] = base + lane;
+      act_b[rank] = bl;
+    }
+    wave_sync();
+    for (int b0 = 0; b0 < nact; b0 += PERB) {
+      const int na = min(PERB, nact - b0);
+      const int a = lane / NX, i = lane - a * NX;
+      if (a < na) wb[a * NX + i] = I.W[(int64_t)act_c[b0 + a] * NX + i];
       wave_sync();
       for (int idx = lane; idx < NX * NX; idx += NRTO_WAVE) {
-        const int i = idx / NX, j = idx - i * NX;
-        q.V[idx] += rho * q.tmp[i] * q.tmp[j];
+        const int r = idx / NX, c = idx - r * NX;
+        double sum = 0.0;
+        for (int aa = 0; aa < na; ++aa) sum += wb[aa * NX + r] * wb[aa * NX + c];
+        q.V[idx] += rho * sum;
       }
-      if (lane < NX) q.v[lane] += rho * be * q.tmp[lane];
+      if (lane < NX) {
+        double sum = 0.0;
+        for (int aa = 0; aa < na; ++aa) sum += act_b[b0 + aa] * wb[aa * NX + lane];
+        q.v[lane] += rho * sum;
+      }
       wave_sync();
     }
   }
 }
 
-// Stage data of the Riccati passes: A_k (NX*NX) then B_k (NX*NU), staged in LDS
-// one stage ahead (each lane holds its share of the next stage in registers
-// while the current stage is computed).
+// Stage data of the backward Riccati pass: A_k (NX*NX), B_k (NX*NU), the
+// nominal x_k (NX) and u_k (NU), staged in LDS one stage ahead (each lane holds
+// its share of the next stage in registers while the current one is computed).
 template <int NX, int NU>
 struct StagePrefetch {
-  static constexpr int N = NX * NX + NX * NU;
+  static constexpr int NA = NX * NX, NB = NX * NU;
+  static constexpr int N = NA + NB + NX + NU;
   static constexpr int PER = (N + NRTO_WAVE - 1) / NRTO_WAVE;
   double v[PER];
-  __device__ void load(const double* A, const double* B) {
+  __device__ void load(const double* A, const double* B, const double* xk, const double* uk) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int idx = lane_id() + i * NRTO_WAVE;
-      v[i] = (idx < NX * NX) ? A[idx] : ((idx < N) ? B[idx - NX * NX] : 0.0);
+      double val = 0.0;
+      if (idx < NA) val = A[idx];
+      else if (idx < NA + NB) val = B[idx - NA];
+      else if (idx < NA + NB + NX) val = xk[idx - NA - NB];
+      else if (idx < N) val = uk[idx - NA - NB - NX];
+      v[i] = val;
+    }
+  }
+  __device__ void store(double* dst) const {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int idx = lane_id() + i * NRTO_WAVE;
+      if (idx < N) dst[idx] = v[i];
+    }
+  }
+};
+
+// Stage data of the forward rollout: A_k, B_k and the stage's gains G_k
+// (NU*(NX+1)), staged one stage ahead.
+template <int NX, int NU>
+struct FwdPrefetch {
+  static constexpr int NA = NX * NX, NB = NX * NU;
+  static constexpr int N = NA + NB + NU * (NX + 1);
+  static constexpr int PER = (N + NRTO_WAVE - 1) / NRTO_WAVE;
+  double v[PER];
+  __device__ void load(const double* A, const double* B, const double* G) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int idx = lane_id() + i * NRTO_WAVE;
+      double val = 0.0;
+      if (idx < NA) val = A[idx];
+      else if (idx < NA + NB) val = B[idx - NA];
+      else if (idx < N) val = G[idx - NA - NB];
+      v[i] = val;
     }
   }
   __device__ void store(double* dst) const {
@@ -1116,13 +1210,20 @@ __device__ void riccati(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double r
   const int T = I.T;
   StagePrefetch<NX, NU> pf;
   StageFlags fl, fln;
-  pf.load(I.A + (int64_t)(T - 1) * NX * NX, I.B + (int64_t)(T - 1) * NX * NU);
+  auto stage_load = [&](int k) {
+    pf.load(I.A + (int64_t)k * NX * NX, I.B + (int64_t)k * NX * NU, I.xhat + (int64_t)k * NX,
+            I.uhat + (int64_t)k * NU);
+  };
+  stage_load(T - 1);
   fl.load(I, T, -1);
   fln.load(I, T - 1, T - 1);
   // LDS copies of the stage-invariant cost data
   for (int idx = lane; idx < NX * NX; idx += NRTO_WAVE) q.Qs[idx] = I.Q[idx];
   for (int idx = lane; idx < NU * NU; idx += NRTO_WAVE) q.Rs[idx] = I.Ru[idx];
-  if (lane < NX) q.xg[lane] = I.xg[lane];
+  if (lane < NX) {
+    q.xg[lane] = I.xg[lane];
+    q.tmp[lane] = I.xhat[T * NX + lane];
+  }
   wave_sync();
   // terminal cost-to-go
   for (int idx = lane; idx < NX * NX; idx += NRTO_WAVE) {
@@ -1131,7 +1232,7 @@ __device__ void riccati(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double r
   }
   if (lane < NX) {
     double s = 0.0;
-    for (int j = 0; j < NX; ++j) s += q.Qs[lane * NX + j] * (I.xhat[T * NX + j] - q.xg[j]);
+    for (int j = 0; j < NX; ++j) s += q.Qs[lane * NX + j] * (q.tmp[j] - q.xg[j]);
     q.v[lane] = 2.0 * s;
   }
   pf.store(q.AB[(T - 1) & 1]);
@@ -1141,9 +1242,11 @@ __device__ void riccati(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double r
   for (int k = T - 1; k >= 0; --k) {
     const double* A = q.AB[k & 1];
     const double* B = A + NX * NX;
+    const double* xk = B + NX * NU;
+    const double* uk = xk + NX;
     fl = fln;
     if (k > 0) {
-      pf.load(I.A + (int64_t)(k - 1) * NX * NX, I.B + (int64_t)(k - 1) * NX * NU);
+      stage_load(k - 1);
       fln.load(I, k - 1, k - 1);
     }
     for (int idx = lane; idx < NX * NX; idx += NRTO_WAVE) {
@@ -1178,7 +1281,7 @@ __device__ void riccati(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double r
     if (lane < NU) {
       double s = 0.0;
 #pragma unroll
-      for (int w = 0; w < NU; ++w) s += q.Rs[lane * NU + w] * I.uhat[k * NU + w];
+      for (int w = 0; w < NU; ++w) s += q.Rs[lane * NU + w] * uk[w];
       s *= 2.0;
 #pragma unroll
       for (int i = 0; i < NX; ++i) s += B[i * NU + lane] * q.v[i];
@@ -1186,27 +1289,29 @@ __device__ void riccati(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double r
     }
     wave_sync();
     {
-      // active control bounds of stage k (flags prefetched a stage ahead)
+      // active control bounds of stage k: flags, beta * sign and input index were
+      // prefetched a stage ahead by the lane of each cone
       uint64_t cmask = __ballot(fl.cf);
-      if (lane == 0) {
-        for (int base = fl.c0; base < fl.c1; base += NRTO_WAVE) {
-          if (base > fl.c0) {
-            cmask = 0;
-            for (int b = 0; b < NRTO_WAVE && base + b < fl.c1; ++b)
-              if (I.C(CA_ACT, base + b) != 0.0) cmask |= 1ull << b;
-          }
-          while (cmask) {
-            const int bit = __ffsll((unsigned long long)cmask) - 1;
-            cmask &= cmask - 1;
-            const int c = base + bit;
-            const int32_t* m = I.cm + c * CM_N;
-            const int i = m[CM_CIDX];
-            q.Huu[i * NU + i] += rho;
-            q.hu[i] += rho * I.C(CA_BETA, c) * (double)m[CM_CSIGN];
-          }
+      while (cmask) {
+        const int bit = __ffsll((unsigned long long)cmask) - 1;
+        cmask &= cmask - 1;
+        const int i = __shfl(fl.ccidx, bit, NRTO_WAVE);
+        const double hb = __shfl(fl.cbs, bit, NRTO_WAVE);
+        if (lane == 0) {
+          q.Huu[i * NU + i] += rho;
+          q.hu[i] += rho * hb;
         }
-        for (int i = 0; i < NU * NU; ++i) q.L[i] = q.Huu[i];
-        chol_inplace<NU>(q.L);
+      }
+      if (lane == 0) {
+        for (int c = fl.c0 + NRTO_WAVE; c < fl.c1; ++c) {   // control cones beyond the first 64
+          if (I.C(CA_ACT, c) == 0.0) continue;
+          const int32_t* m = I.cm + c * CM_N;
+          const int i = m[CM_CIDX];
+          q.Huu[i * NU + i] += rho;
+          q.hu[i] += rho * I.C(CA_BETA, c) * (double)m[CM_CSIGN];
+        }
+        for (int i = 0; i < NU * NU; ++i) q.Lc[i] = q.Huu[i];
+        chol_inplace<NU>(q.Lc);
       }
     }
     wave_sync();
@@ -1215,7 +1320,7 @@ __device__ void riccati(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double r
       double z[NU];
 #pragma unroll
       for (int u = 0; u < NU; ++u) z[u] = (lane < NX) ? q.Hux[u * NX + lane] : q.hu[u];
-      chol_solve<NU>(q.L, z);
+      chol_solve<NU>(q.Lc, z);
 #pragma unroll
       for (int u = 0; u < NU; ++u) {
         gk[u * (NX + 1) + lane] = -z[u];
@@ -1238,7 +1343,7 @@ __device__ void riccati(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double r
       double vv = 0.0;
       if (lane < NX) {
         double s = 0.0;
-        for (int j = 0; j < NX; ++j) s += q.Qs[lane * NX + j] * (I.xhat[k * NX + j] - q.xg[j]);
+        for (int j = 0; j < NX; ++j) s += q.Qs[lane * NX + j] * (xk[j] - q.xg[j]);
         s *= 2.0;
 #pragma unroll
         for (int l = 0; l < NX; ++l) s += A[l * NX + lane] * q.v[l];
@@ -1261,33 +1366,48 @@ __device__ void riccati(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double r
       wave_sync();
     }
   }
-  // forward rollout from dx_0 = 0; the stage's A, B are staged in LDS one stage ahead
-  if (lane < NX) I.dx2[lane] = 0.0;
-  pf.load(I.A, I.B);
-  pf.store(q.AB[0]);
+  // forward rollout from dx_0 = 0: the stage's A, B and gains are staged in LDS
+  // one stage ahead; the current state and control stay in LDS (q.tmp), their
+  // global copies are only written
+  FwdPrefetch<NX, NU> fp;
+  auto fwd_load = [&](int k) {
+    fp.load(I.A + (int64_t)k * NX * NX, I.B + (int64_t)k * NX * NU, I.ric + (int64_t)k * NU * (NX + 1));
+  };
+  if (lane < NX) {
+    q.tmp[lane] = 0.0;
+    I.dx2[lane] = 0.0;
+  }
+  fwd_load(0);
+  fp.store(q.AB[0]);
   wave_sync();
   for (int k = 0; k < T; ++k) {
     const double* A = q.AB[k & 1];
     const double* B = A + NX * NX;
-    if (k + 1 < T) pf.load(I.A + (int64_t)(k + 1) * NX * NX, I.B + (int64_t)(k + 1) * NX * NU);
-    const double* gk = I.ric + (int64_t)k * NU * (NX + 1);
-    const double* xk = I.dx2 + (int64_t)k * NX;
+    const double* gk = B + NX * NU;
+    if (k + 1 < T) fwd_load(k + 1);
     if (lane < NU) {
       double s = gk[lane * (NX + 1) + NX];
 #pragma unroll
-      for (int j = 0; j < NX; ++j) s += gk[lane * (NX + 1) + j] * xk[j];
+      for (int j = 0; j < NX; ++j) s += gk[lane * (NX + 1) + j] * q.tmp[j];
+      q.tmp[NX + lane] = s;
       I.du2[k * NU + lane] = s;
     }
     wave_sync();
+    double xn = 0.0;
     if (lane < NX) {
       double s = 0.0;
 #pragma unroll
-      for (int j = 0; j < NX; ++j) s += A[lane * NX + j] * xk[j];
+      for (int j = 0; j < NX; ++j) s += A[lane * NX + j] * q.tmp[j];
 #pragma unroll
-      for (int u = 0; u < NU; ++u) s += B[lane * NU + u] * I.du2[k * NU + u];
-      I.dx2[(k + 1) * NX + lane] = s;
+      for (int u = 0; u < NU; ++u) s += B[lane * NU + u] * q.tmp[NX + u];
+      xn = s;
     }
-    if (k + 1 < T) pf.store(q.AB[(k + 1) & 1]);
+    wave_sync();
+    if (lane < NX) {
+      q.tmp[lane] = xn;
+      I.dx2[(k + 1) * NX + lane] = xn;
+    }
+    if (k + 1 < T) fp.store(q.AB[(k + 1) & 1]);
     wave_sync();
   }
 }
@@ -1470,7 +1590,9 @@ __device__ void rollout_dx(const Inst<NX, NU, F>& I) {
 }
 
 template <int NX, int NU, typename F>
-__device__ int qp_block(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double rho) {
+__device__ __noinline__ int qp_block(const Inst<NX, NU, F> I, QPScratch<NX, NU> q, double rho) {
+  // compiled out of line with its instance view and LDS carve-up by value: the
+  // pointers live in registers and carry their address spaces
   // Trust-region multiplier: mu = 0 if psi(0) = ||F_u du(0)|| <= r, else the
   // root of phi(mu) = 1/r - 1/psi(mu), which increases with mu and is close to
   // linear in it (exactly so when F_u'F_u acts on one eigen-direction of the
@@ -1858,7 +1980,7 @@ __device__ void cold_state(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts
 }
 
 template <int NX, int NU, typename F, int METHOD>
-__device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, char* smem) {
+__device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, L<char>* smem) {
   Inst<NX, NU, F> I = make_inst<NX, NU, F>(g, ii);
   const int W = blockDim.x / NRTO_WAVE;
   Smem<F> S = carve<F>(smem, I.T, NX, NU, W);
@@ -2097,7 +2219,7 @@ template <int NX, int NU, typename F>
 __global__ void __launch_bounds__(NRTO_SOLVER_MAX_THREADS)
 warm_kernel(DevPtrs g, SolveOpts o, const int32_t* order, int n, const float* pred, int64_t ld, int test,
             int32_t* accepted, double* res) {
-  char* smem = nrto_dyn_smem;
+  L<char>* smem = (L<char>*)nrto_dyn_smem;
   const int ii = order[blockIdx.x];
   Inst<NX, NU, F> I = make_inst<NX, NU, F>(g, ii);
   const int W = blockDim.x / NRTO_WAVE;
@@ -2171,7 +2293,7 @@ hipError_t launch_warm(const DevPtrs& g, const SolveOpts& o, int nx, const int32
 
 template <int NX, int NU, typename F, int METHOD>
 __global__ void __launch_bounds__(NRTO_SOLVER_MAX_THREADS) solve_kernel(DevPtrs g, SolveOpts o, const int32_t* order, int n) {
-  char* smem = nrto_dyn_smem;
+  L<char>* smem = (L<char>*)nrto_dyn_smem;
   const int ii = order[blockIdx.x];
   solve_instance<NX, NU, F, METHOD>(g, o, ii, smem);
 }
