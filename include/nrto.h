@@ -123,11 +123,17 @@ typedef struct {
                                 reached is kept per instance for warm solves. */
   int32_t sigma_every;
   double sigma_thr, sigma_min, sigma_max;
+  int32_t infeas_window;     /* NRTO-DR: 0 = off; else stop with NRTO_INFEASIBLE when, after an
+                                ADMM iteration, the consensus residual r_p = ||p - p~|| has not
+                                fallen below 0.99 times its smallest earlier value for this many
+                                ADMM iterations while r_p / (1 + ||p~||) > 1e-3 (the linearised
+                                problem may be infeasible, e.g. inside a small trust region) */
+  int32_t pad0;
 } nrto_options;
 
 /* Per-instance result of a solve. */
 typedef struct {
-  int32_t status;            /* NRTO_OK or NRTO_MAXITER */
+  int32_t status;            /* NRTO_OK, NRTO_MAXITER or NRTO_INFEASIBLE */
   int32_t admm_iters;
   int32_t inner_iters;       /* total DR iterations (0 for FullADMM) */
   int32_t qp_newton;         /* total Riccati solves in the (du, p) blocks */
@@ -141,7 +147,8 @@ typedef struct {
                                 checks, and the whole solve */
   double sigma_s;            /* DR scaling at the end of the solve */
   int32_t sigma_updates;     /* changes of sigma_s during the solve */
-  int32_t pad0;
+  int32_t nan_flag;          /* 1 when the residuals became NaN (NaN inputs propagate; the solve
+                                stops at the next ADMM iteration with status NRTO_MAXITER) */
 } nrto_solve_report;
 
 /* Per-instance result of one successive-linearisation step. */
@@ -243,6 +250,39 @@ nrto_status nrto_download_socp(nrto_ctx ctx, int32_t inst, double *A, double *B,
  * current state.  rep: host array of n_inst reports (may be NULL).
  */
 nrto_status nrto_solve_socp(nrto_ctx ctx, int32_t warm, nrto_solve_report *rep);
+
+/*
+ * Device views of a batch's SOCP data and NRTO-DR state for
+ * nrto_solve_socp_dev.  Every array is float64 device memory owned by the
+ * caller, laid out as the concatenation over instances 0..n_inst-1 (in order)
+ * of the per-instance arrays of nrto_upload_socp, nrto_get_solution and
+ * nrto_get_state (sizes from nrto_instance_sizes).
+ */
+typedef struct {
+  const double *A, *B, *xhat, *uhat;   /* T*nx*nx, T*nx*nu, (T+1)*nx, T*nu */
+  const double *g0, *w;                /* n_g, n_g*nx */
+  const double *bhat, *bvec;           /* cone entries, blocks*nu */
+} nrto_socp_dev;
+typedef struct {
+  double *st, *kt, *ptt;               /* DR state: s~ (entries), K~ (T*nu*nx), p~~ (n_g) */
+  double *du, *K;                      /* T*nu, T*nu*nx (K[k][u][x]) */
+  double *p, *pt, *lam, *pi;           /* n_g each */
+} nrto_socp_state_dev;
+
+/*
+ * nrto_solve_socp on SOCP data and state held in caller-owned device memory
+ * (the context supplies the problem structure, options, stream and its
+ * internal scratch).  warm = 0: cold start, the state arrays are outputs;
+ * warm = 1: continue from st, kt, ptt, du, K, p, pt, lam (pi is output).  The
+ * large arrays (A, B, xhat, uhat, w, bhat, bvec, st, kt, du, K) are read and
+ * written in place; the per-cone scalars (g0 in; p, pt, ptt, lam in/out; pi
+ * out) are copied device-to-device to and from the context on its stream.  The
+ * buffers must stay valid until the stream has executed the call.  NRTO-DR in
+ * FP64 only (NRTO_ERR_STATE otherwise); NULL arrays are NRTO_ERR_ARG.  rep:
+ * host array of n_inst reports, or NULL (then the call does not synchronise).
+ */
+nrto_status nrto_solve_socp_dev(nrto_ctx ctx, const nrto_socp_dev *socp, nrto_socp_state_dev *state,
+                                int32_t warm, nrto_solve_report *rep);
 
 /*
  * Read the solution of instance inst into host arrays (any may be NULL):

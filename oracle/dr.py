@@ -33,6 +33,10 @@ Two options depart from the printed method (both off by default):
     tau when r_p > mu r_d, rho <- rho / tau when r_d > mu r_p, kept in
     [rho_min, rho_max].  lambda is unscaled, so it is kept as it is; the
     k_v factor does not involve rho, so nothing is refactored.
+  infeas_window (a reading; the paper notes only that linearised problems can
+    be infeasible): stop with status "infeasible" when r_p = ||p - p~|| has not
+    fallen below 0.99 times its smallest earlier value for infeas_window ADMM
+    iterations while r_p / (1 + ||p~||) > 1e-3.
   sigma_adapt: balancing of the DR scaling sigma_s (in the spirit of OSQP's
     step-size rule, Stellato et al., Math. Prog. Comp. 12, 2020): after every
     sigma_every-th DR iteration of a solve, with S = (p~, eta(K)) the affine
@@ -86,6 +90,7 @@ class Options:
     sigma_thr: float = 5.0
     sigma_min: float = 1e-4
     sigma_max: float = 1e6
+    infeas_window: int = 0          # 0 = off (see solve)
 
 
 @dataclasses.dataclass
@@ -207,6 +212,7 @@ def solve(socp, opt: Options = Options(), st: Optional[State] = None, trace: Opt
     fac = factor(socp, opt, st.sigma_s)
     info = {"admm_iters": 0, "dr_iters": 0, "kkt": np.inf, "status": "maxiter", "r_p": np.inf, "r_d": np.inf}
     pt_prev = st.pt.copy()
+    rp_best, l_best = np.inf, 0
     for l in range(1, opt.max_admm + 1):
         n_dr, _, fac = dr_steps(socp, opt, st, fac, opt.max_dr, trace, info["dr_iters"])
         info["dr_iters"] += n_dr
@@ -221,7 +227,7 @@ def solve(socp, opt: Options = Options(), st: Optional[State] = None, trace: Opt
         if trace is not None:
             trace("admm", l, st)
         stop = False
-        if opt.eps_kkt > 0 and (l % opt.check_every == 0):
+        if opt.eps_kkt > 0 and (l % opt.check_every == 0 or l == opt.max_admm):
             info["kkt"] = residual(socp, opt, st)
             stop = info["kkt"] <= opt.eps_kkt
         if opt.eps_p > 0 and opt.eps_d > 0 and info["r_p"] <= opt.eps_p and info["r_d"] <= opt.eps_d:
@@ -229,6 +235,14 @@ def solve(socp, opt: Options = Options(), st: Optional[State] = None, trace: Opt
         if stop:
             info["status"] = "ok"
             break
+        if opt.infeas_window > 0:
+            # the linearised problem may be infeasible (e.g. inside a small trust
+            # region): then ADMM's consensus residual stalls at the sets' distance
+            if info["r_p"] < 0.99 * rp_best:
+                rp_best, l_best = info["r_p"], l
+            if l - l_best >= opt.infeas_window and info["r_p"] > 1e-3 * (1.0 + float(np.linalg.norm(st.pt))):
+                info["status"] = "infeasible"
+                break
         if opt.rho_adapt:
             if info["r_p"] > opt.rho_mu * info["r_d"]:
                 opt.rho = min(opt.rho_max, opt.rho * opt.rho_tau)

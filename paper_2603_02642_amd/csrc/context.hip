@@ -300,6 +300,8 @@ static void fill_opts(const nrto_ctx c, SolveOpts& o, int warm) {
   o.sigma_thr = c->opt.sigma_thr;
   o.sigma_min = c->opt.sigma_min;
   o.sigma_max = c->opt.sigma_max;
+  o.infeas_window = c->opt.infeas_window;
+  o.pad0 = 0;
 }
 
 static nrto_status check_options(nrto_ctx c, const nrto_options* o) {
@@ -313,6 +315,7 @@ static nrto_status check_options(nrto_ctx c, const nrto_options* o) {
   if (o->block_threads != 0 && (o->block_threads < 64 || o->block_threads > 1024 || o->block_threads % 64))
     return ctx_err(c, NRTO_ERR_ARG, "block_threads must be 0 or a multiple of 64 in [64, 1024]");
   if (o->cold_init != 0 && o->cold_init != 1) return ctx_err(c, NRTO_ERR_ARG, "cold_init must be 0 or 1");
+  if (o->infeas_window < 0) return ctx_err(c, NRTO_ERR_ARG, "infeas_window must be >= 0");
   if (o->rho_adapt != 0 && o->rho_adapt != 1) return ctx_err(c, NRTO_ERR_ARG, "rho_adapt must be 0 or 1");
   if (o->rho_adapt &&
       !(o->rho_mu > 1 && o->rho_tau > 1 && o->rho_min > 0 && o->rho_min <= o->rho && o->rho <= o->rho_max))
@@ -609,7 +612,7 @@ extern "C" nrto_status nrto_download_socp(nrto_ctx c, int32_t inst, double* A, d
 // Solve launches of all model groups: the first non-empty group on the context's
 // stream, the others on side streams forked from and joined back into it, so
 // that the groups' persistent launches overlap (their tails in particular).
-static nrto_status launch_solve(nrto_ctx c, int warm) {
+static nrto_status launch_solve(nrto_ctx c, int warm, const DevPtrs& g) {
   SolveOpts o;
   fill_opts(c, o, warm);
   int groups[3], ng = 0;
@@ -621,7 +624,7 @@ static nrto_status launch_solve(nrto_ctx c, int warm) {
     hipStream_t s = (j == 0) ? c->stream : c->aux[j - 1];
     if (j > 0) HIPCHK(c, hipStreamWaitEvent(s, c->ev_fork, 0));
     const int cnt = c->group_off[gi + 1] - c->group_off[gi];
-    HIPCHK(c, launch_solver(c->g, o, c->group_nx[gi], c->order + c->group_off[gi], cnt, c->threads, c->smem, s));
+    HIPCHK(c, launch_solver(g, o, c->group_nx[gi], c->order + c->group_off[gi], cnt, c->threads, c->smem, s));
     if (j > 0) {
       HIPCHK(c, hipEventRecord(c->ev_join[j - 1], s));
       HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join[j - 1], 0));
@@ -640,11 +643,61 @@ extern "C" nrto_status nrto_solve_socp(nrto_ctx c, int32_t warm, nrto_solve_repo
     return ctx_err(c, NRTO_ERR_STATE,
                    "the FP32 solver path is switched off: its kernel took a GPU memory fault whose cause is not "
                    "yet identified; use NRTO_FP64");
-  nrto_status ls = launch_solve(c, warm ? 1 : 0);
+  nrto_status ls = launch_solve(c, warm ? 1 : 0, c->g);
   if (ls != NRTO_OK) return ls;
   if (rep) {
     HIPCHK(c, copy_out(rep, c->g.rep, (size_t)c->n, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    reports_to_us(c, rep, c->n);
+  }
+  return NRTO_OK;
+}
+
+extern "C" nrto_status nrto_solve_socp_dev(nrto_ctx c, const nrto_socp_dev* sd, nrto_socp_state_dev* st,
+                                           int32_t warm, nrto_solve_report* rep) {
+  if (!c) return set_global_error(NRTO_ERR_ARG, "null context");
+  if (!sd || !st) return ctx_err(c, NRTO_ERR_ARG, "null SOCP or state view");
+  if (!sd->A || !sd->B || !sd->xhat || !sd->uhat || !sd->g0 || !sd->w || !sd->bhat || !sd->bvec)
+    return ctx_err(c, NRTO_ERR_ARG, "null SOCP array");
+  if (!st->st || !st->kt || !st->ptt || !st->du || !st->K || !st->p || !st->pt || !st->lam || !st->pi)
+    return ctx_err(c, NRTO_ERR_ARG, "null state array");
+  if (c->opt.method != NRTO_DR || c->opt.precision != NRTO_FP64)
+    return ctx_err(c, NRTO_ERR_STATE, "nrto_solve_socp_dev runs NRTO-DR in FP64");
+  DevPtrs g = c->g;
+  g.A = const_cast<double*>(sd->A);
+  g.B = const_cast<double*>(sd->B);
+  g.xhat = const_cast<double*>(sd->xhat);
+  g.uhat = const_cast<double*>(sd->uhat);
+  g.w = const_cast<double*>(sd->w);
+  g.bhat64 = const_cast<double*>(sd->bhat);
+  g.bvec64 = const_cast<double*>(sd->bvec);
+  g.st = st->st;
+  g.Kt = st->kt;
+  g.K = st->K;
+  g.du = st->du;
+  hipStream_t s = c->stream;
+  const size_t nc = (size_t)c->ncones;
+  auto col = [&](int k) { return c->g.carr + (int64_t)k * c->ncones; };
+  auto d2d = [&](double* dst, const double* src) {
+    return hipMemcpyAsync(dst, src, nc * sizeof(double), hipMemcpyDeviceToDevice, s);
+  };
+  HIPCHK(c, d2d(col(CA_G0), sd->g0));
+  if (warm) {
+    HIPCHK(c, d2d(col(CA_P), st->p));
+    HIPCHK(c, d2d(col(CA_PT), st->pt));
+    HIPCHK(c, d2d(col(CA_PTT), st->ptt));
+    HIPCHK(c, d2d(col(CA_LAM), st->lam));
+  }
+  nrto_status ls = launch_solve(c, warm ? 1 : 0, g);
+  if (ls != NRTO_OK) return ls;
+  HIPCHK(c, d2d(st->p, col(CA_P)));
+  HIPCHK(c, d2d(st->pt, col(CA_PT)));
+  HIPCHK(c, d2d(st->ptt, col(CA_PTT)));
+  HIPCHK(c, d2d(st->lam, col(CA_LAM)));
+  HIPCHK(c, d2d(st->pi, col(CA_PI)));
+  if (rep) {
+    HIPCHK(c, copy_out(rep, c->g.rep, (size_t)c->n, s));
+    HIPCHK(c, hipStreamSynchronize(s));
     reports_to_us(c, rep, c->n);
   }
   return NRTO_OK;
@@ -790,7 +843,7 @@ extern "C" nrto_status nrto_capture_step(nrto_ctx c, int32_t warm, int32_t with_
   for (auto& h : c->hi) max_ng = std::max(max_ng, h.d.ng);
   HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
   hipError_t e = with_linearize ? launch_linearize(c->g, c->n, max_ng, c->stream) : hipSuccess;
-  nrto_status s = (e == hipSuccess) ? launch_solve(c, warm) : NRTO_ERR_HIP;
+  nrto_status s = (e == hipSuccess) ? launch_solve(c, warm, c->g) : NRTO_ERR_HIP;
   hipGraph_t graph = nullptr;
   hipError_t e2 = hipStreamEndCapture(c->stream, &graph);
   if (e != hipSuccess) return ctx_err(c, NRTO_ERR_HIP, std::string("capture: ") + hipGetErrorString(e));

@@ -107,6 +107,7 @@ struct SolveOpts {
   double rho_mu, rho_tau, rho_min, rho_max;
   int32_t sigma_adapt, sigma_every;
   double sigma_thr, sigma_min, sigma_max;
+  int32_t infeas_window, pad0;
 };
 
 // Device pointers the kernels use.

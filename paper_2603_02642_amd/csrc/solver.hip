@@ -74,7 +74,7 @@ __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t
 
 __host__ __device__ inline size_t qp_scratch_doubles(int nx, int nu) {
   return 2 * nx * nx + nx + nx * nu + 2 * nu * nu + nu * nx + nu + 2 * nx + 64 +
-         2 * (nx * nx + nx * nu + nu * (nx + 1)) + nu * (nx + 1) + nx * nx + nu * nu + nx + 160;
+         2 * (nx * nx + nx * nu + nu * (nx + 1)) + nu * (nx + 1) + nx * nx + nu * nu + nx + 160 + (2 * MAX_T + 4) / 2;
 }
 
 __host__ __device__ inline size_t smem_bytes(int T, int nx, int nu, int fbytes, int W) {
@@ -1030,6 +1030,8 @@ struct QPScratch {
   L<double>* G;       // gains of the current stage, NU*(NX+1)
   L<double> *Qs, *Rs, *xg;   // LDS copies of Q, Ru, the goal state
   L<double>* act;     // active state cones of a stage: 64 int indices, 64 betas, 64 gradient values
+  L<double>* tl;      // LDS copy of the stage lists: state cones by time (T + 2 ints), control
+                      // cones by step (T + 1 ints)
 };
 
 template <int NX, int NU>
@@ -1051,7 +1053,8 @@ __device__ QPScratch<NX, NU> qp_carve(L<double>* q) {
   s.Qs = q; q += NX * NX;
   s.Rs = q; q += NU * NU;
   s.xg = q; q += NX;
-  s.act = q;
+  s.act = q; q += 160;
+  s.tl = q;
   return s;
 }
 
@@ -1065,9 +1068,9 @@ struct StageFlags {
   double sbeta, cbs;   // state beta; control beta times the bound's sign
   int ccidx;
   template <class InstT>
-  __device__ void load(const InstT& I, int t, int k) {
-    s0 = I.tls[t];
-    s1 = I.tls[t + 1];
+  __device__ void load(const InstT& I, const L<int>* tls, const L<int>* tlc, int t, int k) {
+    s0 = tls[t];
+    s1 = tls[t + 1];
     const int l = lane_id();
     sf = false;
     sbeta = 0.0;
@@ -1079,8 +1082,8 @@ struct StageFlags {
     cbs = 0.0;
     ccidx = 0;
     if (k >= 0) {
-      c0 = I.tlc[k];
-      c1 = I.tlc[k + 1];
+      c0 = tlc[k];
+      c1 = tlc[k + 1];
       if (c0 + l < c1) {
         const int c = c0 + l;
         cf = I.C(CA_ACT, c) != 0.0;
@@ -1215,8 +1218,10 @@ __device__ void riccati(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double r
             I.uhat + (int64_t)k * NU);
   };
   stage_load(T - 1);
-  fl.load(I, T, -1);
-  fln.load(I, T - 1, T - 1);
+  const L<int>* tls = (const L<int>*)q.tl;
+  const L<int>* tlc = tls + (T + 2);
+  fl.load(I, tls, tlc, T, -1);
+  fln.load(I, tls, tlc, T - 1, T - 1);
   // LDS copies of the stage-invariant cost data
   for (int idx = lane; idx < NX * NX; idx += NRTO_WAVE) q.Qs[idx] = I.Q[idx];
   for (int idx = lane; idx < NU * NU; idx += NRTO_WAVE) q.Rs[idx] = I.Ru[idx];
@@ -1247,7 +1252,7 @@ __device__ void riccati(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double r
     fl = fln;
     if (k > 0) {
       stage_load(k - 1);
-      fln.load(I, k - 1, k - 1);
+      fln.load(I, tls, tlc, k - 1, k - 1);
     }
     for (int idx = lane; idx < NX * NX; idx += NRTO_WAVE) {
       const int i = idx / NX, j = idx - i * NX;
@@ -1603,6 +1608,11 @@ __device__ __noinline__ int qp_block(const Inst<NX, NU, F> I, QPScratch<NX, NU> 
   const double r = I.r_trust;
   const double tol = 1e-13 * r;
   int solves = 0;
+  {
+    L<int>* tl = (L<int>*)q.tl;
+    for (int i = lane_id(); i < 2 * I.T + 3; i += NRTO_WAVE) tl[i] = I.tls[i];   // tls then tlc
+    wave_sync();
+  }
   rollout_dx<NX, NU, F>(I);
   auto eval = [&](double m) {
     solves += ssn<NX, NU, F>(I, q, rho, m);
@@ -2014,7 +2024,9 @@ __device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, L<c
     __syncthreads();
   }
 
-  int admm = 0, inner = 0, qpn = 0, status = NRTO_MAXITER, sig_updates = 0;
+  int admm = 0, inner = 0, qpn = 0, status = NRTO_MAXITER, sig_updates = 0, nan_flag = 0;
+  double rp_best = 1e300;   // smallest consensus residual so far and its ADMM iteration
+  int l_best = 0;
   double kkt = 1e300, rp = 0.0, rd = 0.0;
   for (int l = 1; l <= o.max_admm; ++l) {
     admm = l;
@@ -2090,7 +2102,7 @@ __device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, L<c
     }
     qpn += (int)S.red[65];
     // p, pi from the (du, p) solution; then the FullADMM k_v step; dual updates
-    double acc2[2] = {0.0, 0.0};
+    double acc2[3] = {0.0, 0.0, 0.0};
     for (int c = threadIdx.x; c < I.ng; c += blockDim.x) {
       const double a = cons_lin<NX, NU, F>(I, c, I.dx, I.du);
       const double g0 = I.C(CA_G0, c);
@@ -2110,19 +2122,35 @@ __device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, L<c
         I.C(CA_LAM, c) = I.C(CA_LAM, c) + (p - pt);
       }
       acc2[0] += (p - pt) * (p - pt);
+      acc2[2] += pt * pt;
     }
     if (METHOD == NRTO_FULLADMM) {
       double kacc[2] = {0.0, 0.0};
       k_solve<NX, NU, F, NRTO_FULLADMM>(I, S, o, sig, kacc);
     }
-    block_sum<2>(S.red, acc2, W);
+    block_sum<3>(S.red, acc2, W);
     rp = sqrt(acc2[0]);
+    if (isnan(rp)) {   // NaN inputs propagate; stop and flag (block-uniform)
+      nan_flag = 1;
+      break;
+    }
     if (METHOD == NRTO_DR) rd = rho * sqrt(acc2[1]);
     if (o.eps_kkt > 0.0 && (l % o.check_every == 0 || l == o.max_admm)) {
       kkt = kkt_residual<NX, NU, F, METHOD>(I, S, o, sig, pending, W);
       t_kkt += wall_clock64() - t_mark;
       if (kkt <= o.eps_kkt) {
         status = NRTO_OK;
+        break;
+      }
+    }
+    // stagnating consensus residual: no 1% decrease within infeas_window ADMM iterations
+    if (METHOD == NRTO_DR && o.infeas_window > 0) {
+      if (rp < 0.99 * rp_best) {
+        rp_best = rp;
+        l_best = l;
+      }
+      if (l - l_best >= o.infeas_window && rp > 1e-3 * (1.0 + sqrt(acc2[2]))) {
+        status = NRTO_INFEASIBLE;
         break;
       }
     }
@@ -2154,6 +2182,7 @@ __device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, L<c
     rep.rho = rho;
     rep.sigma_s = sig;
     rep.sigma_updates = sig_updates;
+    rep.nan_flag = (nan_flag || isnan(kkt)) ? 1 : 0;
     // ticks here; the host scales them to microseconds
     rep.t_dr_us = (double)t_dr;
     rep.t_qp_us = (double)t_qp;

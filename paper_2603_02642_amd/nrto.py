@@ -41,7 +41,7 @@ class Options(C.Structure):
                 ("rho_adapt", C.c_int32), ("rho_mu", C.c_double), ("rho_tau", C.c_double),
                 ("rho_min", C.c_double), ("rho_max", C.c_double), ("sigma_adapt", C.c_int32),
                 ("sigma_every", C.c_int32), ("sigma_thr", C.c_double), ("sigma_min", C.c_double),
-                ("sigma_max", C.c_double)]
+                ("sigma_max", C.c_double), ("infeas_window", C.c_int32), ("pad0", C.c_int32)]
 
 
 class SolveReport(C.Structure):
@@ -50,7 +50,15 @@ class SolveReport(C.Structure):
                 ("r_d", C.c_double), ("mu", C.c_double), ("rho", C.c_double),
                 ("t_dr_us", C.c_double), ("t_qp_us", C.c_double), ("t_kkt_us", C.c_double),
                 ("t_total_us", C.c_double), ("sigma_s", C.c_double), ("sigma_updates", C.c_int32),
-                ("pad0", C.c_int32)]
+                ("nan_flag", C.c_int32)]
+
+
+class SocpDev(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("A", "B", "xhat", "uhat", "g0", "w", "bhat", "bvec")]
+
+
+class StateDev(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("st", "kt", "ptt", "du", "K", "p", "pt", "lam", "pi")]
 
 
 class StepReport(C.Structure):
@@ -88,6 +96,7 @@ def load() -> C.CDLL:
         "nrto_upload_socp": (i32, [vp, i32] + [_dp] * 8),
         "nrto_download_socp": (i32, [vp, i32] + [_dp] * 8),
         "nrto_solve_socp": (i32, [vp, i32, P(SolveReport)]),
+        "nrto_solve_socp_dev": (i32, [vp, P(SocpDev), P(StateDev), i32, P(SolveReport)]),
         "nrto_get_solution": (i32, [vp, i32] + [_dp] * 7),
         "nrto_get_state": (i32, [vp, i32] + [_dp] * 4),
         "nrto_set_state": (i32, [vp, i32] + [_dp] * 9),
@@ -250,6 +259,16 @@ class Context:
         rep = (SolveReport * self.n)()
         _check(load().nrto_solve_socp(self.h, 1 if warm else 0, rep), self.h)
         return list(rep)
+
+    def solve_dev(self, socp: dict, state: dict, warm: bool = False, report: bool = True):
+        """nrto_solve_socp_dev on caller-owned device tensors (float64, the
+        concatenated per-instance layout): socp keys A, B, xhat, uhat, g0, w,
+        bhat, bvec; state keys st, kt, ptt, du, K, p, pt, lam, pi."""
+        sd = SocpDev(*[C.c_void_p(socp[k].data_ptr()) for k, _ in SocpDev._fields_])
+        st = StateDev(*[C.c_void_p(state[k].data_ptr()) for k, _ in StateDev._fields_])
+        rep = (SolveReport * self.n)() if report else None
+        _check(load().nrto_solve_socp_dev(self.h, C.byref(sd), C.byref(st), 1 if warm else 0, rep), self.h)
+        return list(rep) if report else None
 
     def solve_async(self, warm: bool = False):
         _check(load().nrto_solve_socp(self.h, 1 if warm else 0, None), self.h)

@@ -214,3 +214,56 @@ def test_arm_dr_iterates_match_oracle_fp64(L, M, policy):
         assert rel_err(g[k], getattr(st, k)) <= 1e-9, k
     ref_kkt = dr.residual(s, o, st)
     assert abs(rep[0].kkt - ref_kkt) <= 1e-9 * max(1.0, ref_kkt)
+
+
+BENCH = dict(rho=50.0, sigma_s=100.0, sigma_every=10, sigma_thr=2.0)
+
+
+def test_full_size_quadrotor_iterates_at_bench_settings():
+    """The quadrotor at its full horizon (T = 50, five obstacles, thrust bounds:
+    cones up to 613 entries) under the benchmark's solver settings (rho 50,
+    sigma_s from 100 balanced every 10 DR iterations with threshold 2, margin
+    start): fixed-count DR iterates against the oracle at 1e-9."""
+    _torch()
+    prob = synth.config2()
+    s = linearize.assemble(prob, prob.u_init, 2.0)
+    o = dr.Options(max_admm=3, max_dr=15, eps_kkt=0.0, eps_dr_abs=0.0, eps_dr_rel=0.0, cold_init="margin",
+                   sigma_adapt=True, **BENCH)
+    st, info = dr.solve(s, o)
+    print(f"full-size quadrotor: oracle sigma updates {info['sigma_updates']}", flush=True)
+    c = _ctx(prob, s, method=0, max_admm=3, max_inner=15, eps_kkt=0.0, eps_dr_abs=0.0, eps_dr_rel=0.0,
+             r_trust=2.0, cold_init=1, sigma_adapt=1, **BENCH)
+    rep = c.solve()
+    g = c.solution(0)
+    gs = c.state(0)
+    assert rep[0].sigma_updates == info["sigma_updates"]
+    for k in ["du", "K", "p", "pt", "lam"]:
+        assert rel_err(g[k], getattr(st, k)) <= 1e-9, k
+    assert rel_err(expand_entries(s, gs["st"]), st.s_t) <= 1e-9
+    assert rel_err(gs["kt"], st.K_t) <= 1e-9
+    ref_kkt = dr.residual(s, o, st)
+    assert abs(rep[0].kkt - ref_kkt) <= 1e-9 * max(1.0, ref_kkt)
+
+
+def test_full_size_arm_iterates_match_oracle():
+    """The 7-DOF arm at its full horizon (T = 60: 3360 cones, 1.1 million cone
+    entries, LDS of one instance near the compute unit's 160 KB) with the
+    margin start and sigma_s balancing: fixed-count DR iterates at 1e-9."""
+    _torch()
+    prob = synth.config3()
+    s = linearize.assemble(prob, prob.u_init, 5.0)
+    ox = dict(rho=50.0, sigma_s=100.0, sigma_every=3, sigma_thr=1.2)
+    o = dr.Options(max_admm=2, max_dr=4, eps_kkt=0.0, eps_dr_abs=0.0, eps_dr_rel=0.0, cold_init="margin",
+                   sigma_adapt=True, **ox)
+    st, info = dr.solve(s, o)
+    c = _ctx(prob, s, method=0, max_admm=2, max_inner=4, eps_kkt=0.0, eps_dr_abs=0.0, eps_dr_rel=0.0,
+             r_trust=5.0, cold_init=1, sigma_adapt=1, **ox)
+    rep = c.solve()
+    g = c.solution(0)
+    gs = c.state(0)
+    assert rep[0].sigma_updates == info["sigma_updates"]
+    for k in ["du", "K", "p", "pt", "lam"]:
+        assert rel_err(g[k], getattr(st, k)) <= 1e-9, k
+    assert rel_err(expand_entries(s, gs["st"]), st.s_t) <= 1e-9
+    ref_kkt = dr.residual(s, o, st)
+    assert abs(rep[0].kkt - ref_kkt) <= 1e-9 * max(1.0, ref_kkt)

@@ -53,8 +53,10 @@ def _config2():
     return synth.config2(), 2.0
 
 
-# tuned NRTO-DR settings (open-loop cold point, rho 200, sigma_s 10) on both sides
-TUNED = dict(rho=200.0, sigma_s=10.0)
+# the benchmark's NRTO-DR settings on both sides: rho 50, sigma_s from 100
+# balanced every 10 DR iterations (threshold 2), the KKT residual checked every
+# 5 ADMM iterations (and at the last one)
+TUNED = dict(rho=50.0, sigma_s=100.0, sigma_every=10, sigma_thr=2.0, check_every=5)
 
 
 @pytest.mark.parametrize("make,method,prec,cold", [(_near_obstacle, 0, 0, 0), (_near_obstacle, 0, 0, 1),
@@ -69,7 +71,7 @@ def test_solve_to_tolerance_checked_by_oracle(make, method, prec, cold):
     prob, r = make()
     s = linearize.assemble(prob, prob.u_init, r)
     o = nrto.default_options(method=method, precision=prec, max_admm=400, max_inner=200, eps_kkt=1e-4,
-                             cold_init=cold, r_trust=r, **TUNED)
+                             cold_init=cold, r_trust=r, sigma_adapt=1 if method == 0 else 0, **TUNED)
     if prec == 1:
         o.eps_dr_abs = o.eps_dr_rel = 1e-5
     c = nrto.Context([prob], o)
@@ -78,18 +80,30 @@ def test_solve_to_tolerance_checked_by_oracle(make, method, prec, cold):
     assert rep.kkt <= 1e-4 and rep.status == 0
     g = c.solution(0)
     gs = c.state(0)
-    res = _gpu_point_residual(s, g, gs, method, o.rho, o.sigma_s)
+    res = _gpu_point_residual(s, g, gs, method, o.rho, rep.sigma_s)   # the DR scaling the solve ended with
     assert res <= (1.5e-4 if prec == 0 else 5e-4), res
     # same point as the oracle's own solve, at the accuracy both reach
     if method == 1:
         st, info = fulladmm.solve(s, fulladmm.Options(max_admm=400, eps_kkt=1e-4))
     else:
-        st, info = dr.solve(s, dr.Options(max_admm=400, max_dr=200, eps_kkt=1e-4,
+        st, info = dr.solve(s, dr.Options(max_admm=400, max_dr=200, eps_kkt=1e-4, sigma_adapt=True,
                                           cold_init="margin" if cold else "zero", **TUNED))
     assert info["kkt"] <= 1e-4
-    assert rel_err(g["du"], st.du) <= 5e-2
-    if prec == 0:
-        assert abs(rep.admm_iters - info["admm_iters"]) <= 1
+    print(f"solve to tolerance: device {rep.admm_iters} ADMM / {rep.inner_iters} DR, oracle "
+          f"{info['admm_iters']} / {info.get('dr_iters')}", flush=True)
+    err = rel_err(g["du"], st.du)
+    print(f"  du relative difference {err:.3e}", flush=True)
+    if prec == 0 and rep.admm_iters == info["admm_iters"]:
+        # the same iterations to the same stop: the same point up to FP64 rounding
+        assert err <= 1e-7
+    elif prec == 0:
+        # over a long solve the DR-scaling balancing may decide differently on
+        # the two sides (rounding at its thresholds): two points that both meet
+        # the 1e-4 residual
+        assert abs(rep.admm_iters - info["admm_iters"]) <= 4 * TUNED["check_every"]
+        assert err <= 1e-2
+    else:
+        assert err <= 5e-2
 
 
 @pytest.mark.skip(reason=FP32_OFF)
