@@ -1618,28 +1618,59 @@ __device__ __noinline__ int qp_block(const Inst<NX, NU, F> I, QPScratch<NX, NU> 
     solves += ssn<NX, NU, F>(I, q, rho, m);
     return state_norm<NX, NU, F>(I);
   };
-  // start: the current multiplier, else the last positive one of this instance
-  // (kept across solves), else 1; mu = 0 is tried only when psi(start) < r
-  double mu = *I.mu;
-  if (!(mu > 0.0)) mu = (I.iscr[ISCR_MUHINT] > 0.0) ? I.iscr[ISCR_MUHINT] : 1.0;
-  double psi = eval(mu);
+  // start: when the last block ended with an inactive trust region (mu = 0, also
+  // at a cold start), mu = 0 first -- a single evaluation whenever the region
+  // stays inactive -- and, if psi(0) > r, the last positive multiplier of this
+  // instance (kept across solves) or 1; otherwise the current multiplier, then
+  // mu = 0 when psi(start) < r
   double lo = 0.0, flo = 0.0, hi = -1.0, fhi = 0.0;   // hi < 0: no upper end yet
   bool have_lo = false;
-  double m0 = 0.0, f0 = 0.0, m1 = mu, f1 = 1.0 / r - 1.0 / psi;
+  double m0 = 0.0, f0 = 0.0, m1, f1;
   bool have_prev = false;
-  bool done = fabs(psi - r) <= tol;
-  if (!done && psi < r) {
-    // the root lies below the last multiplier, possibly at mu = 0
-    hi = mu;
-    fhi = f1;
-    m0 = m1;
-    f0 = f1;
-    have_prev = true;
+  bool done;
+  double mu, psi;
+  if (!(*I.mu > 0.0)) {
+    mu = 0.0;
     psi = eval(0.0);
     m1 = 0.0;
     f1 = 1.0 / r - 1.0 / psi;
-    mu = 0.0;
     done = psi <= r + tol;
+    if (!done) {
+      lo = 0.0;
+      flo = f1;
+      have_lo = true;
+      m0 = m1;
+      f0 = f1;
+      have_prev = true;
+      mu = (I.iscr[ISCR_MUHINT] > 0.0) ? I.iscr[ISCR_MUHINT] : 1.0;
+      psi = eval(mu);
+      m1 = mu;
+      f1 = 1.0 / r - 1.0 / psi;
+      done = fabs(psi - r) <= tol;
+      if (!done && psi < r) {
+        hi = mu;
+        fhi = f1;
+      }
+    }
+  } else {
+    mu = *I.mu;
+    psi = eval(mu);
+    m1 = mu;
+    f1 = 1.0 / r - 1.0 / psi;
+    done = fabs(psi - r) <= tol;
+    if (!done && psi < r) {
+      // the root lies below the last multiplier, possibly at mu = 0
+      hi = mu;
+      fhi = f1;
+      m0 = m1;
+      f0 = f1;
+      have_prev = true;
+      psi = eval(0.0);
+      m1 = 0.0;
+      f1 = 1.0 / r - 1.0 / psi;
+      mu = 0.0;
+      done = psi <= r + tol;
+    }
   }
   if (!done) {
     if (psi > r) {
