@@ -247,6 +247,35 @@ def config5_instance(i: int, split: str = "train") -> Problem:
     return quadrotor(stream_seed(key, i), T=50, n_obs=10, x0_pos=x0p, goal_pos=gp)
 
 
+# Sweeps shaped like the paper's unicycle / quadrotor sweep table: horizon T,
+# uncertainty level tau and obstacle count varied one at a time around
+# (T0, tau0, O0) = (30, 0.05, 0), step 25 ms.  The level is used as the radius of
+# the disturbance ball (as the batch workloads' radii 0.02 / 0.05); goals and
+# obstacles are scaled to what the systems reach in T * 25 ms.
+TABLE1_NOMINAL = (30, 0.05, 0)
+TABLE1_SWEEPS = {"T": (30, 45, 60), "tau": (0.025, 0.05, 0.075), "obs": (0, 3, 5)}
+
+
+def table1_instance(model: str, T: int, tau: float, n_obs: int, i: int) -> Problem:
+    """Instance i of one sweep point; model 'unicycle' (goal (1, 1, 0), obstacles
+    with centres U[0.25, 0.75]^2 and radii U[0.04, 0.08]) or 'quadrotor' (goal
+    position (1, 1, 1), centres U[0.25, 0.75]^3, radii U[0.04, 0.08]); ball
+    radius tau; dt = 0.025."""
+    mid = 0 if model == "unicycle" else 1
+    seed = stream_seed(7, mid, T, int(round(tau * 1000)), n_obs, i)
+    d = Draws(stream_seed(7, mid, i, 1))
+    if model == "unicycle":
+        p = unicycle(seed, T=T, n_obs=0, radius=tau)
+        p.xg = np.array([1.0, 1.0, 0.0])
+        p.obstacles = _draw_obstacles(d, n_obs, 2, 0.25, 0.75, 0.04, 0.08, [p.x0[:2], p.xg[:2]], margin=0.1)
+    else:
+        p = quadrotor(seed, T=T, n_obs=0, radius=tau, goal_pos=np.array([1.0, 1.0, 1.0]))
+        p.obstacles = _draw_obstacles(d, n_obs, 3, 0.25, 0.75, 0.04, 0.08, [p.x0[:3], p.xg[:3]], margin=0.1)
+    p.dt = 0.025
+    p.name = f"{model} T={T} tau={tau} obs={n_obs}"
+    return p
+
+
 def mlp_features(p: Problem) -> np.ndarray:
     """Network input for the warm start: x0 (12), goal (12), 10 x (centre, radius)."""
     f = np.zeros(64)
