@@ -1,13 +1,14 @@
 // Warm-start network: GELU MLP with BF16 GEMM operands on the gfx950 matrix
-// cores (v_mfma_f32_16x16x16_bf16), FP32 accumulation, FP32 master weights and
+// cores (v_mfma_f32_16x16x32_bf16), FP32 accumulation, FP32 master weights and
 // Adam.  Forward, backward and optimizer kernels are all here.
 //
 // GEMM: C[M x N] = A[M x K] B[K x N] with A and B read through (row, column)
 // strides, so the forward product (A W'), the input gradient (dZ W) and the
 // weight gradient (dZ' A) share one kernel.  A 256-thread workgroup computes a
 // 64 x 64 tile; each wave a 32 x 32 sub-tile as 2 x 2 MFMA 16x16 blocks; K is
-// staged through LDS in chunks of 32 (operand layouts: A rows x k, B stored
-// column-major so both fragments are 4 consecutive bf16 per lane).
+// staged through LDS in chunks of 64 with 16-byte loads along whichever index
+// of an operand is contiguous (A as rows x k, B as columns x k, so both
+// fragments are 8 consecutive bf16 per lane).
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -18,7 +19,6 @@
 
 namespace nrto {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
@@ -36,15 +36,70 @@ __device__ __forceinline__ float gelu_grad_f(float x) {
 
 enum { EPI_STORE = 0, EPI_BIAS_GELU = 1, EPI_BIAS = 2 };
 
-constexpr int GT_M = 64, GT_N = 64, GT_K = 32, GT_PAD = 4;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
+constexpr int GT_M = 64, GT_N = 64, GT_K = 64, GT_PAD = 8;
+
+// Stage a GT_ROWS x GT_K tile of an operand X (X[r][k] = X[r * sr + k * sk],
+// r < R, k < K) into LDS as tile[r][k] (k contiguous).  Vector loads of 8
+// bf16 along k when k is the contiguous index, along r when r is; otherwise
+// (or at a ragged edge) one element at a time.
+template <int ROWS>
+__device__ __forceinline__ void stage_tile(uint16_t (*tile)[GT_K + GT_PAD], const uint16_t* __restrict__ X, int64_t sr,
+                                           int64_t sk, int r0, int k0, int R, int K, int tid) {
+  const bool kvec = (sk == 1) && (sr % 8 == 0) && ((((uintptr_t)X) & 15) == 0);
+  const bool rvec = !kvec && (sr == 1) && (sk % 8 == 0) && ((((uintptr_t)X) & 15) == 0);
+  if (kvec) {
+    for (int v = tid; v < ROWS * GT_K / 8; v += 256) {
+      const int r = v / (GT_K / 8), c = (v - r * (GT_K / 8)) * 8;
+      const int gr = r0 + r, gk = k0 + c;
+      u16x8 val;
+      if (gr < R && gk + 8 <= K) {
+        val = *(const u16x8*)(X + (int64_t)gr * sr + gk);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) val[j] = (gr < R && gk + j < K) ? X[(int64_t)gr * sr + gk + j] : (uint16_t)0;
+      }
+      *(u16x8*)&tile[r][c] = val;
+    }
+  } else if (rvec) {
+    for (int v = tid; v < ROWS * GT_K / 8; v += 256) {
+      const int c = v / (ROWS / 8), r = (v - c * (ROWS / 8)) * 8;
+      const int gr = r0 + r, gk = k0 + c;
+      u16x8 val;
+      if (gk < K && gr + 8 <= R) {
+        val = *(const u16x8*)(X + gr + (int64_t)gk * sk);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) val[j] = (gk < K && gr + j < R) ? X[gr + j + (int64_t)gk * sk] : (uint16_t)0;
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) tile[r + j][c] = val[j];
+    }
+  } else {
+    for (int idx = tid; idx < ROWS * GT_K; idx += 256) {
+      const int r = idx / GT_K, c = idx - r * GT_K;
+      const int gr = r0 + r, gk = k0 + c;
+      tile[r][c] = (gr < R && gk < K) ? X[(int64_t)gr * sr + (int64_t)gk * sk] : (uint16_t)0;
+    }
+  }
+}
+
+// GEMM C = A B on the gfx950 matrix cores (v_mfma_f32_16x16x32_bf16): a
+// 256-work-item workgroup computes a 64 x 64 tile, each wave a 32 x 32
+// sub-tile as 2 x 2 blocks of 16 x 16; K is staged through LDS 64 at a time.
+// A lane feeds 8 consecutive k of one row of A and of one column of B (the same
+// k for both operands, so the product does not depend on how the instruction
+// assigns k to lanes); the 16 x 16 result block leaves lane l with rows
+// 4 (l / 16) + r, r < 4, of column l % 16.
 template <int EPI>
 __global__ void __launch_bounds__(256)
 gemm_bf16_kernel(const uint16_t* __restrict__ A, int64_t sam, int64_t sak, const uint16_t* __restrict__ B,
                  int64_t sbk, int64_t sbn, int M, int N, int K, float* __restrict__ C, int64_t ldc,
                  const float* __restrict__ bias, uint16_t* __restrict__ Cb) {
-  __shared__ uint16_t As[GT_M][GT_K + GT_PAD];
-  __shared__ uint16_t Bs[GT_N][GT_K + GT_PAD];
+  __shared__ __align__(16) uint16_t As[GT_M][GT_K + GT_PAD];
+  __shared__ __align__(16) uint16_t Bs[GT_N][GT_K + GT_PAD];
   const int m0 = blockIdx.y * GT_M, n0 = blockIdx.x * GT_N;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -54,35 +109,24 @@ gemm_bf16_kernel(const uint16_t* __restrict__ A, int64_t sam, int64_t sak, const
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   for (int k0 = 0; k0 < K; k0 += GT_K) {
-    for (int idx = tid; idx < GT_M * GT_K; idx += 256) {
-      const int r = idx / GT_K, c = idx - r * GT_K;
-      const int gm = m0 + r, gk = k0 + c;
-      As[r][c] = (gm < M && gk < K) ? A[gm * sam + gk * sak] : (uint16_t)0;
-    }
-    for (int idx = tid; idx < GT_N * GT_K; idx += 256) {
-      const int r = idx / GT_K, c = idx - r * GT_K;   // r: column n, c: k
-      const int gn = n0 + r, gk = k0 + c;
-      Bs[r][c] = (gn < N && gk < K) ? B[gk * sbk + gn * sbn] : (uint16_t)0;
-    }
+    stage_tile<GT_M>(As, A, sam, sak, m0, k0, M, K, tid);
+    stage_tile<GT_N>(Bs, B, sbn, sbk, n0, k0, N, K, tid);   // B staged as [n][k]
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < GT_K; kk += 16) {
-      bf16x4 a[2], b[2];
+    for (int kk = 0; kk < GT_K; kk += 32) {
+      bf16x8 a[2], b[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        const uint16_t* pa = &As[wm * 32 + i * 16 + (lane & 15)][kk + 4 * (lane >> 4)];
-        const uint16_t* pb = &Bs[wn * 32 + i * 16 + (lane & 15)][kk + 4 * (lane >> 4)];
-        a[i] = bf16x4{(short)pa[0], (short)pa[1], (short)pa[2], (short)pa[3]};
-        b[i] = bf16x4{(short)pb[0], (short)pb[1], (short)pb[2], (short)pb[3]};
+        a[i] = __builtin_bit_cast(bf16x8, *(const u16x8*)&As[wm * 32 + i * 16 + (lane & 15)][kk + 8 * (lane >> 4)]);
+        b[i] = __builtin_bit_cast(bf16x8, *(const u16x8*)&Bs[wn * 32 + i * 16 + (lane & 15)][kk + 8 * (lane >> 4)]);
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
-  // D fragment: lane holds rows 4*(lane/16) + r (r < 4) of column lane % 16
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll

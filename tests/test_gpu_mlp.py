@@ -31,7 +31,9 @@ def _bits_to_f64(b):
 
 
 @pytest.mark.parametrize("M,N,K,trans_a,trans_b", [(64, 64, 32, False, False), (77, 45, 50, False, True),
-                                                  (130, 200, 96, True, False), (5, 3800, 256, False, True)])
+                                                  (130, 200, 96, True, False), (5, 3800, 256, False, True),
+                                                  (136, 72, 104, True, False), (200, 136, 88, False, True),
+                                                  (256, 1400, 256, False, True)])
 def test_gemm_bf16_matches_exact_product(M, N, K, trans_a, trans_b):
     torch = _torch()
     from paper_2603_02642_amd import nrto
