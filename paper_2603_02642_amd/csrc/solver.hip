@@ -1294,78 +1294,99 @@ __device__ void riccati(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double r
     }
     wave_sync();
     {
-      // active control bounds of stage k: flags, beta * sign and input index were
-      // prefetched a stage ahead by the lane of each cone
+      // gains of stage k: every lane factors H_uu (plus rho on the diagonal of
+      // the active control bounds, whose flags, beta * sign and input index were
+      // prefetched a stage ahead by the lane of each cone) in registers, and
+      // lanes 0..NX solve one right-hand side each (the columns of H_ux, then h_u)
+      double Hl[NU * NU], hl[NU];
+#pragma unroll
+      for (int i = 0; i < NU * NU; ++i) Hl[i] = q.Huu[i];
+#pragma unroll
+      for (int u = 0; u < NU; ++u) hl[u] = q.hu[u];
       uint64_t cmask = __ballot(fl.cf);
       while (cmask) {
         const int bit = __ffsll((unsigned long long)cmask) - 1;
         cmask &= cmask - 1;
-        const int i = __shfl(fl.ccidx, bit, NRTO_WAVE);
+        const int ci = __shfl(fl.ccidx, bit, NRTO_WAVE);
         const double hb = __shfl(fl.cbs, bit, NRTO_WAVE);
-        if (lane == 0) {
-          q.Huu[i * NU + i] += rho;
-          q.hu[i] += rho * hb;
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+          if (u == ci) {
+            Hl[u * NU + u] += rho;
+            hl[u] += rho * hb;
+          }
         }
       }
-      if (lane == 0) {
-        for (int c = fl.c0 + NRTO_WAVE; c < fl.c1; ++c) {   // control cones beyond the first 64
-          if (I.C(CA_ACT, c) == 0.0) continue;
-          const int32_t* m = I.cm + c * CM_N;
-          const int i = m[CM_CIDX];
-          q.Huu[i * NU + i] += rho;
-          q.hu[i] += rho * I.C(CA_BETA, c) * (double)m[CM_CSIGN];
+      for (int c = fl.c0 + NRTO_WAVE; c < fl.c1; ++c) {   // control cones beyond the first 64
+        if (I.C(CA_ACT, c) == 0.0) continue;
+        const int ci = I.cm[c * CM_N + CM_CIDX];
+        const double hb = I.C(CA_BETA, c) * (double)I.cm[c * CM_N + CM_CSIGN];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+          if (u == ci) {
+            Hl[u * NU + u] += rho;
+            hl[u] += rho * hb;
+          }
         }
-        for (int i = 0; i < NU * NU; ++i) q.Lc[i] = q.Huu[i];
-        chol_inplace<NU>(q.Lc);
       }
-    }
-    wave_sync();
-    double* gk = I.ric + (int64_t)k * NU * (NX + 1);
-    if (lane <= NX) {
-      double z[NU];
+      chol_inplace<NU>(Hl);
+      double* gk = I.ric + (int64_t)k * NU * (NX + 1);
+      if (lane <= NX) {
+        double z[NU];
 #pragma unroll
-      for (int u = 0; u < NU; ++u) z[u] = (lane < NX) ? q.Hux[u * NX + lane] : q.hu[u];
-      chol_solve<NU>(q.Lc, z);
+        for (int u = 0; u < NU; ++u) z[u] = (lane < NX) ? q.Hux[u * NX + lane] : hl[u];
+        chol_solve<NU>(Hl, z);
 #pragma unroll
-      for (int u = 0; u < NU; ++u) {
-        gk[u * (NX + 1) + lane] = -z[u];
-        q.G[u * (NX + 1) + lane] = -z[u];
+        for (int u = 0; u < NU; ++u) {
+          gk[u * (NX + 1) + lane] = -z[u];
+          q.G[u * (NX + 1) + lane] = -z[u];
+        }
       }
     }
     wave_sync();
     if (k > 0) {
-      double nv[(NX * NX + NRTO_WAVE - 1) / NRTO_WAVE];
+      // cost-to-go of stage k: V = 2Q + mu I + A'(V A) + H_ux' G_x is symmetric;
+      // its upper triangle is computed and written to both halves
+      constexpr int NTRI = NX * (NX + 1) / 2;
+      double nv[(NTRI + NRTO_WAVE - 1) / NRTO_WAVE];
+      int ti[(NTRI + NRTO_WAVE - 1) / NRTO_WAVE], tj[(NTRI + NRTO_WAVE - 1) / NRTO_WAVE];
       int n = 0;
-      for (int idx = lane; idx < NX * NX; idx += NRTO_WAVE, ++n) {
-        const int i = idx / NX, j = idx - i * NX;
-        double s = 2.0 * q.Qs[idx] + (i == j ? mu : 0.0);
+      for (int idx = lane; idx < NTRI; idx += NRTO_WAVE, ++n) {
+        int i = 0, rem = idx;   // row i of the upper triangle holds NX - i entries
+        while (rem >= NX - i) {
+          rem -= NX - i;
+          ++i;
+        }
+        const int j = i + rem;
+        double sum = 2.0 * q.Qs[i * NX + j] + (i == j ? mu : 0.0);
 #pragma unroll
-        for (int l = 0; l < NX; ++l) s += A[l * NX + i] * q.PA[l * NX + j];
+        for (int l = 0; l < NX; ++l) sum += A[l * NX + i] * q.PA[l * NX + j];
 #pragma unroll
-        for (int u = 0; u < NU; ++u) s += q.Hux[u * NX + i] * q.G[u * (NX + 1) + j];
-        nv[n] = s;
+        for (int u = 0; u < NU; ++u) sum += q.Hux[u * NX + i] * q.G[u * (NX + 1) + j];
+        nv[n] = sum;
+        ti[n] = i;
+        tj[n] = j;
       }
       double vv = 0.0;
       if (lane < NX) {
-        double s = 0.0;
-        for (int j = 0; j < NX; ++j) s += q.Qs[lane * NX + j] * (xk[j] - q.xg[j]);
-        s *= 2.0;
+        double sum = 0.0;
+        for (int j = 0; j < NX; ++j) sum += q.Qs[lane * NX + j] * (xk[j] - q.xg[j]);
+        sum *= 2.0;
 #pragma unroll
-        for (int l = 0; l < NX; ++l) s += A[l * NX + lane] * q.v[l];
+        for (int l = 0; l < NX; ++l) sum += A[l * NX + lane] * q.v[l];
 #pragma unroll
-        for (int u = 0; u < NU; ++u) s += q.Hux[u * NX + lane] * q.G[u * (NX + 1) + NX];
-        vv = s;
+        for (int u = 0; u < NU; ++u) sum += q.Hux[u * NX + lane] * q.G[u * (NX + 1) + NX];
+        vv = sum;
+      }
+      // V, v are not read by the products above (only V A, H_ux and G): update in place
+      n = 0;
+      for (int idx = lane; idx < NTRI; idx += NRTO_WAVE, ++n) {
+        q.V[ti[n] * NX + tj[n]] = nv[n];
+        q.V[tj[n] * NX + ti[n]] = nv[n];
       }
       wave_sync();
-      n = 0;
-      for (int idx = lane; idx < NX * NX; idx += NRTO_WAVE, ++n) q.PA[idx] = nv[n];
       if (lane < NX) q.v[lane] = vv;
       pf.store(q.AB[(k - 1) & 1]);
-      wave_sync();
-      for (int idx = lane; idx < NX * NX; idx += NRTO_WAVE) {
-        const int i = idx / NX, j = idx - i * NX;
-        q.V[idx] = 0.5 * (q.PA[i * NX + j] + q.PA[j * NX + i]);
-      }
       wave_sync();
       add_state_terms<NX, NU, F>(I, q, fl, rho);
       wave_sync();
