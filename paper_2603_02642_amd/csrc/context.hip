@@ -50,7 +50,7 @@ struct nrto_ctx_s {
   DevPtrs g{};
   std::vector<void*> allocs;
   int64_t ncones = 0, nent = 0, nbv = 0, nA = 0, nB = 0, nX = 0, nU = 0, nK = 0, nW = 0, nP = 0, nTL = 0,
-          nG = 0, nR = 0, ntask = 0;
+          nG = 0, ntask = 0;
   int32_t* order = nullptr;
   std::vector<int32_t> horder;
   int group_nx[3] = {3, 12, 14};
@@ -405,7 +405,6 @@ extern "C" nrto_status nrto_setup(const nrto_problem* probs, int32_t n, const nr
     d.oP = c->nP; c->nP += (int64_t)h.prm.size();
     d.oTL = c->nTL; c->nTL += (int64_t)h.tl.size();
     d.oG = c->nG; c->nG += (int64_t)d.T * d.nu * d.nu;
-    d.oR = c->nR; c->nR += (int64_t)d.T * d.nu * (d.nx + 1);
   }
   DevPtrs& g = c->g;
   g.ncones = c->ncones;
@@ -439,7 +438,6 @@ extern "C" nrto_status nrto_setup(const nrto_problem* probs, int32_t n, const nr
   ALLOC(g.K, c->nK);
   ALLOC(g.Kt, c->nK);
   ALLOC(g.kscr, c->nK);
-  ALLOC(g.ric, c->nR);
   ALLOC(g.prm, c->nP);
   ALLOC(g.tl, c->nTL);
   ALLOC(g.gch, c->nG);

@@ -38,7 +38,6 @@ struct InstDev {
                    //             x_lo nx, x_hi nx, inertia 3, links 7, obstacles n_obs*4
   int64_t oTL;     // time lists: state cones by t (T+2), control cones by k (T+1)
   int64_t oG;      // block Cholesky factors: T*nu*nu
-  int64_t oR;      // Riccati gains: T*nu*(nx+1)
   double radius, r_trust, dt, mass;
 };
 
@@ -133,7 +132,6 @@ struct DevPtrs {
   double* K;           // gains (double)
   double* Kt;          // DR K~
   double* kscr;        // KKT accumulation of sum_j A_hat_j' zeta_j (double)
-  double* ric;         // Riccati gains (offset oR)
   double* prm;
   int32_t* tl;
   double* gch;

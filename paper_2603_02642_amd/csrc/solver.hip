@@ -67,6 +67,8 @@ struct Smem {
   L<double>* red;  // 128: [0, 64) block reductions, [64, 128) broadcast scalars
   L<double>* wscr; // W*128: per-wave cone sums / broadcast
   L<double>* qp;   // wave-0 QP scratch
+  L<double>* gfb;  // Riccati feedback gains, T*NU*NX: [k][u][x] (the LDS of Kf when F is double)
+  L<double>* gff;  // Riccati feedforward gains, T*NU: [k][u]
   L<int>* ctr;     // 4 ints
 };
 
@@ -85,6 +87,8 @@ __host__ __device__ inline size_t smem_bytes(int T, int nx, int nu, int fbytes, 
   s += align16(128 * 8);
   s += align16((size_t)W * 128 * 8);
   s += align16(qp_scratch_doubles(nx, nu) * 8);
+  s += align16((size_t)T * nu * 8);                  // feedforward gains
+  if (fbytes < 8) s += align16((size_t)T * nu * nx * 8);   // feedback gains (else in Kf's LDS)
   s += 16;
   return s;
 }
@@ -99,6 +103,16 @@ __device__ Smem<F> carve(L<char>* base, int T, int nx, int nu, int W) {
   m.red = (L<double>*)(base + o); o += align16(128 * 8);
   m.wscr = (L<double>*)(base + o); o += align16((size_t)W * 128 * 8);
   m.qp = (L<double>*)(base + o); o += align16(qp_scratch_doubles(nx, nu) * 8);
+  m.gff = (L<double>*)(base + o); o += align16((size_t)T * nu * 8);
+  if (sizeof(F) < 8) {
+    m.gfb = (L<double>*)(base + o);
+    o += align16((size_t)T * nu * nx * 8);
+  } else {
+    // Kf is dead while the (du, p) block runs: the next DR K-solve rewrites
+    // all of it before it is read again, and the KKT residual reads K from
+    // global memory
+    m.gfb = (L<double>*)m.Kf;
+  }
   m.ctr = (L<int>*)(base + o);
   return m;
 }
@@ -196,7 +210,7 @@ struct Inst {
   G<F>* st;
   G<F>* nuv;
   const G<double> *A, *B, *xhat, *uhat;
-  G<double> *dx, *du, *dx2, *du2, *K, *Kt, *kscr, *ric;
+  G<double> *dx, *du, *dx2, *du2, *K, *Kt, *kscr;
   const G<double> *Q, *Ru, *RK2, *xg;
   const G<int32_t>* tls;  // state cones by time: [tls[t], tls[t+1])
   const G<int32_t>* tlc;  // control cones by step: [tlc[k], tlc[k+1])
@@ -208,6 +222,106 @@ struct Inst {
 
   __device__ G<double>& C(int a, int j) const { return ca[(int64_t)a * cstride + j]; }
 };
+
+// Wave-uniform copy of a value held in vector registers or on the stack of an
+// out-of-line function (every lane holds the same value).  In scalar registers
+// the compiler keeps such pointers live instead of reloading them from the
+// argument block on the stack inside loops: a stack reload is a vector-memory
+// load, and waiting for it also waits for every global load issued before it
+// (the prefetches of the next stage).
+template <typename P>
+__device__ __forceinline__ P uni(P p) {
+  if constexpr (sizeof(P) == 8) {
+    const uint64_t v = __builtin_bit_cast(uint64_t, p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return __builtin_bit_cast(P, ((uint64_t)hi << 32) | lo);
+  } else {
+    static_assert(sizeof(P) == 4, "32- or 64-bit values");
+    return __builtin_bit_cast(P, (uint32_t)__builtin_amdgcn_readfirstlane(__builtin_bit_cast(uint32_t, p)));
+  }
+}
+
+// Raw buffer view of one array of an instance (wave-uniform base and size in a
+// buffer descriptor).  A load addresses it by a vector offset (here always the
+// lane's fixed offset, a register the loop never rewrites) plus a scalar
+// offset; offsets at or past the end read 0.  Used for the prefetches of the
+// Riccati sweep, whose loads must stay in flight while the wave reuses its
+// other registers.
+template <typename T>
+struct Buf {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __amdgpu_buffer_rsrc_t r;
+#else
+  const T* p;
+#endif
+  // n elements of T starting at p (n * sizeof(T) < 2^31)
+  __device__ static Buf make(const G<T>* p, int64_t n) {
+    Buf b;
+#if defined(__HIP_DEVICE_COMPILE__)
+    // word 3 of a raw (untyped) buffer descriptor on the gfx9 family
+    b.r = __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)(n * (int64_t)sizeof(T)), 0x00020000);
+#else
+    b.p = p;
+    (void)n;
+#endif
+    return b;
+  }
+  // element at byte offset voff + soff
+  __device__ T ld(uint32_t voff, uint32_t soff) const {
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (sizeof(T) == 8)
+      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    else
+      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+#else
+    return *(const T*)((const char*)p + voff + soff);
+#endif
+  }
+};
+
+// The instance view with every member made wave-uniform (see uni).
+template <int NX, int NU, typename F>
+__device__ __forceinline__ Inst<NX, NU, F> uniform_inst(const Inst<NX, NU, F>& I) {
+  Inst<NX, NU, F> U;
+  U.T = uni(I.T);
+  U.ng = uni(I.ng);
+  U.nent = uni(I.nent);
+  U.ntask = uni(I.ntask);
+  U.r = uni(I.r);
+  U.r_trust = uni(I.r_trust);
+  U.cm = uni(I.cm);
+  U.ca = uni(I.ca);
+  U.cstride = uni(I.cstride);
+  U.W = uni(I.W);
+  U.bhat = uni(I.bhat);
+  U.bvec = uni(I.bvec);
+  U.st = uni(I.st);
+  U.nuv = uni(I.nuv);
+  U.A = uni(I.A);
+  U.B = uni(I.B);
+  U.xhat = uni(I.xhat);
+  U.uhat = uni(I.uhat);
+  U.dx = uni(I.dx);
+  U.du = uni(I.du);
+  U.dx2 = uni(I.dx2);
+  U.du2 = uni(I.du2);
+  U.K = uni(I.K);
+  U.Kt = uni(I.Kt);
+  U.kscr = uni(I.kscr);
+  U.Q = uni(I.Q);
+  U.Ru = uni(I.Ru);
+  U.RK2 = uni(I.RK2);
+  U.xg = uni(I.xg);
+  U.tls = uni(I.tls);
+  U.tlc = uni(I.tlc);
+  U.tasks = uni(I.tasks);
+  U.tmask = uni(I.tmask);
+  U.mu = uni(I.mu);
+  U.iscr = uni(I.iscr);
+  U.flags = uni(I.flags);
+  return U;
+}
 
 template <int NX, int NU, typename F>
 __device__ Inst<NX, NU, F> make_inst(const DevPtrs& g, int ii) {
@@ -238,7 +352,6 @@ __device__ Inst<NX, NU, F> make_inst(const DevPtrs& g, int ii) {
   I.K = (G<double>*)(g.K + d.oK);
   I.Kt = (G<double>*)(g.Kt + d.oK);
   I.kscr = (G<double>*)(g.kscr + d.oK);
-  I.ric = (G<double>*)(g.ric + d.oR);
   const double* prm = g.prm + d.oP;
   ParamOffsets po = param_offsets(NX, NU, d.n_obs);
   I.Q = (const G<double>*)(prm + po.Q);
@@ -1025,18 +1138,26 @@ __device__ void fa_commit(const Inst<NX, NU, F>& I, Smem<F>& S) {
 template <int NX, int NU>
 struct QPScratch {
   L<double> *V, *v, *PA, *PB, *Huu, *Hux, *hu, *Lc, *tmp, *red;   // Lc: Cholesky factor of Huu
-  L<double>* AB[2];   // double buffer of one stage's data: A (NX*NX), B (NX*NU), then x_k, u_k
-                   // (backward pass) or the gains G_k (forward rollout)
+  L<double>* AB;      // double buffer of one stage's data, halves of AB_N doubles: A (NX*NX),
+                      // B (NX*NU), then x_k, u_k (backward pass); A and B only in the forward rollout
+  static constexpr int AB_N = NX * NX + NX * NU + NU * (NX + 1);
+  // half (k & 1) of the double buffer (address arithmetic: an array of two
+  // pointers indexed at run time would live on the stack)
+  __device__ L<double>* ab(int k) const { return AB + (k & 1) * AB_N; }
   L<double>* G;       // gains of the current stage, NU*(NX+1)
   L<double> *Qs, *Rs, *xg;   // LDS copies of Q, Ru, the goal state
   L<double>* act;     // active state cones of a stage: 64 int indices, 64 betas, 64 gradient values
   L<double>* tl;      // LDS copy of the stage lists: state cones by time (T + 2 ints), control
                       // cones by step (T + 1 ints)
+  L<double>* gfb;     // gains of all stages: feedback [k][u][x] (T*NU*NX) and
+  L<double>* gff;     // feedforward [k][u] (T*NU), outside the scratch block
 };
 
 template <int NX, int NU>
-__device__ QPScratch<NX, NU> qp_carve(L<double>* q) {
+__device__ QPScratch<NX, NU> qp_carve(L<double>* q, L<double>* gfb, L<double>* gff) {
   QPScratch<NX, NU> s;
+  s.gfb = gfb;
+  s.gff = gff;
   s.V = q; q += NX * NX;
   s.v = q; q += NX;
   s.PA = q; q += NX * NX;
@@ -1047,8 +1168,7 @@ __device__ QPScratch<NX, NU> qp_carve(L<double>* q) {
   s.Lc = q; q += NU * NU;
   s.tmp = q; q += 2 * NX;
   s.red = q; q += 64;
-  s.AB[0] = q; q += NX * NX + NX * NU + NU * (NX + 1);
-  s.AB[1] = q; q += NX * NX + NX * NU + NU * (NX + 1);
+  s.AB = q; q += 2 * QPScratch<NX, NU>::AB_N;
   s.G = q; q += NU * (NX + 1);
   s.Qs = q; q += NX * NX;
   s.Rs = q; q += NU * NU;
@@ -1061,38 +1181,39 @@ __device__ QPScratch<NX, NU> qp_carve(L<double>* q) {
 // Active-set flags of one stage, loaded a stage ahead: lane l holds the flag and
 // beta of state cone tls[t] + l, and the flag, beta, input index and sign of
 // control cone tlc[k] + l (cones beyond the first 64 of a stage are read
-// directly when used).
+// directly when used).  load() only issues the loads: the loaded values are
+// first used a stage later (a use right after the load would wait for it, and
+// with it for every global load issued earlier, such as the stage prefetch).
 struct StageFlags {
   int s0, s1, c0, c1;
-  bool sf, cf;
-  double sbeta, cbs;   // state beta; control beta times the bound's sign
-  int ccidx;
-  template <class InstT>
-  __device__ void load(const InstT& I, const L<int>* tls, const L<int>* tlc, int t, int k) {
-    s0 = tls[t];
-    s1 = tls[t + 1];
-    const int l = lane_id();
-    sf = false;
-    sbeta = 0.0;
-    if (s0 + l < s1) {
-      sf = I.C(CA_ACT, s0 + l) != 0.0;
-      sbeta = I.C(CA_BETA, s0 + l);
-    }
-    cf = false;
-    cbs = 0.0;
-    ccidx = 0;
+  // raw loaded values (lanes past the stage's cones hold whatever follows in
+  // the arrays; the accessors mask them)
+  double sact, sbeta;          // state cone: flag, beta
+  double cact, cbeta;          // control cone: flag, beta
+  int ccidx, ccsign;           // control cone: input index, bound sign
+  __device__ bool sf() const { return lane_id() < s1 - s0 && sact != 0.0; }
+  __device__ bool cf() const { return lane_id() < c1 - c0 && cact != 0.0; }
+  __device__ double cbs() const { return cbeta * (double)ccsign; }   // beta times the bound's sign (lanes with cf())
+  // bact, bbeta: the instance's CA_ACT and CA_BETA columns; bcm: its cone metadata
+  __device__ void load(const Buf<double>& bact, const Buf<double>& bbeta, const Buf<int32_t>& bcm,
+                       const L<int>* tls, const L<int>* tlc, int t, int k) {
+    // the list bounds are wave-uniform (scalar registers): each load below is
+    // a scalar offset plus the lane's fixed offset
+    s0 = uni(tls[t]);
+    s1 = uni(tls[t + 1]);
+    const uint32_t l = (uint32_t)lane_id();
+    sact = bact.ld(l * 8u, (uint32_t)s0 * 8u);
+    sbeta = bbeta.ld(l * 8u, (uint32_t)s0 * 8u);
     if (k >= 0) {
-      c0 = tlc[k];
-      c1 = tlc[k + 1];
-      if (c0 + l < c1) {
-        const int c = c0 + l;
-        cf = I.C(CA_ACT, c) != 0.0;
-        ccidx = I.cm[c * CM_N + CM_CIDX];
-        cbs = I.C(CA_BETA, c) * (double)I.cm[c * CM_N + CM_CSIGN];
-      }
+      c0 = uni(tlc[k]);
+      c1 = uni(tlc[k + 1]);
     } else {
       c0 = c1 = 0;
     }
+    cact = bact.ld(l * 8u, (uint32_t)c0 * 8u);
+    cbeta = bbeta.ld(l * 8u, (uint32_t)c0 * 8u);
+    ccidx = bcm.ld(l * (uint32_t)(CM_N * 4) + CM_CIDX * 4u, (uint32_t)c0 * (uint32_t)(CM_N * 4));
+    ccsign = bcm.ld(l * (uint32_t)(CM_N * 4) + CM_CSIGN * 4u, (uint32_t)c0 * (uint32_t)(CM_N * 4));
   }
 };
 
@@ -1111,7 +1232,7 @@ __device__ void add_state_terms(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, 
     bool f;
     double bl;
     if (base == fl.s0) {
-      f = fl.sf;
+      f = fl.sf();
       bl = fl.sbeta;
     } else {
       f = (base + lane < fl.s1) && I.C(CA_ACT, base + lane) != 0.0;
@@ -1150,23 +1271,19 @@ __device__ void add_state_terms(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, 
 // Stage data of the backward Riccati pass: A_k (NX*NX), B_k (NX*NU), the
 // nominal x_k (NX) and u_k (NU), staged in LDS one stage ahead (each lane holds
 // its share of the next stage in registers while the current one is computed).
-template <int NX, int NU>
-struct StagePrefetch {
-  static constexpr int NA = NX * NX, NB = NX * NU;
-  static constexpr int N = NA + NB + NX + NU;
+// Each array is read lane-strided from its own (wave-uniform) base, so that a
+// load's address is a scalar base plus the lane's fixed offset: the address
+// registers are never overwritten while the loads are in flight.
+template <int N>
+struct LanePrefetch {
   static constexpr int PER = (N + NRTO_WAVE - 1) / NRTO_WAVE;
   double v[PER];
-  __device__ void load(const double* A, const double* B, const double* xk, const double* uk) {
+  // elements [first, first + N) of the array behind b (lanes past N read
+  // whatever follows, or 0 past the array's end; store() drops them)
+  __device__ void load(const Buf<double>& b, int first) {
+    const uint32_t lo = (uint32_t)lane_id() * 8u;
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int idx = lane_id() + i * NRTO_WAVE;
-      double val = 0.0;
-      if (idx < NA) val = A[idx];
-      else if (idx < NA + NB) val = B[idx - NA];
-      else if (idx < NA + NB + NX) val = xk[idx - NA - NB];
-      else if (idx < N) val = uk[idx - NA - NB - NX];
-      v[i] = val;
-    }
+    for (int i = 0; i < PER; ++i) v[i] = b.ld(lo + (uint32_t)(i * NRTO_WAVE * 8), (uint32_t)first * 8u);
   }
   __device__ void store(double* dst) const {
 #pragma unroll
@@ -1177,51 +1294,70 @@ struct StagePrefetch {
   }
 };
 
-// Stage data of the forward rollout: A_k, B_k and the stage's gains G_k
-// (NU*(NX+1)), staged one stage ahead.
+template <int NX, int NU>
+struct StagePrefetch {
+  static constexpr int NA = NX * NX, NB = NX * NU;
+  LanePrefetch<NA> a;
+  LanePrefetch<NB> b;
+  LanePrefetch<NX> x;
+  LanePrefetch<NU> u;
+  // stage k of the arrays A, B, x_hat, u_hat
+  __device__ void load(const Buf<double>& bA, const Buf<double>& bB, const Buf<double>& bx, const Buf<double>& bu,
+                       int k) {
+    a.load(bA, k * NA);
+    b.load(bB, k * NB);
+    x.load(bx, k * NX);
+    u.load(bu, k * NU);
+  }
+  __device__ void store(double* dst) const {
+    a.store(dst);
+    b.store(dst + NA);
+    x.store(dst + NA + NB);
+    u.store(dst + NA + NB + NX);
+  }
+};
+
+// Stage data of the forward rollout: A_k and B_k, staged one stage ahead.
 template <int NX, int NU>
 struct FwdPrefetch {
   static constexpr int NA = NX * NX, NB = NX * NU;
-  static constexpr int N = NA + NB + NU * (NX + 1);
-  static constexpr int PER = (N + NRTO_WAVE - 1) / NRTO_WAVE;
-  double v[PER];
-  __device__ void load(const double* A, const double* B, const double* G) {
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int idx = lane_id() + i * NRTO_WAVE;
-      double val = 0.0;
-      if (idx < NA) val = A[idx];
-      else if (idx < NA + NB) val = B[idx - NA];
-      else if (idx < N) val = G[idx - NA - NB];
-      v[i] = val;
-    }
+  LanePrefetch<NA> a;
+  LanePrefetch<NB> b;
+  // stage k of the arrays A and B
+  __device__ void load(const Buf<double>& bA, const Buf<double>& bB, int k) {
+    a.load(bA, k * NA);
+    b.load(bB, k * NB);
   }
   __device__ void store(double* dst) const {
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int idx = lane_id() + i * NRTO_WAVE;
-      if (idx < N) dst[idx] = v[i];
-    }
+    a.store(dst);
+    b.store(dst + NA);
   }
 };
 
 // Riccati solve of the LQ problem of the current active set at multiplier mu;
-// result in (du2, dx2).
+// result in (du2, dx2).  Compiled out of line (one copy, its own register
+// allocation) with the instance view and LDS carve-up by value.
 template <int NX, int NU, typename F>
-__device__ void riccati(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double rho, double mu) {
+__device__ __noinline__ void riccati(const Inst<NX, NU, F> Iarg, QPScratch<NX, NU> qarg, double rho, double mu) {
+  const Inst<NX, NU, F> I = uniform_inst(Iarg);
+  QPScratch<NX, NU> q = qp_carve<NX, NU>(uni(qarg.V), uni(qarg.gfb), uni(qarg.gff));   // V is the carve-up's base
   const int lane = lane_id();
   const int T = I.T;
   StagePrefetch<NX, NU> pf;
   StageFlags fl, fln;
-  auto stage_load = [&](int k) {
-    pf.load(I.A + (int64_t)k * NX * NX, I.B + (int64_t)k * NX * NU, I.xhat + (int64_t)k * NX,
-            I.uhat + (int64_t)k * NU);
-  };
+  const Buf<double> bA = Buf<double>::make(I.A, (int64_t)T * NX * NX);
+  const Buf<double> bB = Buf<double>::make(I.B, (int64_t)T * NX * NU);
+  const Buf<double> bx = Buf<double>::make(I.xhat, (int64_t)(T + 1) * NX);
+  const Buf<double> bu = Buf<double>::make(I.uhat, (int64_t)T * NU);
+  const Buf<double> bact = Buf<double>::make(&I.C(CA_ACT, 0), I.ng);
+  const Buf<double> bbeta = Buf<double>::make(&I.C(CA_BETA, 0), I.ng);
+  const Buf<int32_t> bcm = Buf<int32_t>::make(I.cm, (int64_t)I.ng * CM_N);
+  auto stage_load = [&](int k) { pf.load(bA, bB, bx, bu, k); };
   stage_load(T - 1);
   const L<int>* tls = (const L<int>*)q.tl;
   const L<int>* tlc = tls + (T + 2);
-  fl.load(I, tls, tlc, T, -1);
-  fln.load(I, tls, tlc, T - 1, T - 1);
+  fl.load(bact, bbeta, bcm, tls, tlc, T, -1);
+  fln.load(bact, bbeta, bcm, tls, tlc, T - 1, T - 1);
   // LDS copies of the stage-invariant cost data
   for (int idx = lane; idx < NX * NX; idx += NRTO_WAVE) q.Qs[idx] = I.Q[idx];
   for (int idx = lane; idx < NU * NU; idx += NRTO_WAVE) q.Rs[idx] = I.Ru[idx];
@@ -1240,20 +1376,26 @@ __device__ void riccati(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double r
     for (int j = 0; j < NX; ++j) s += q.Qs[lane * NX + j] * (q.tmp[j] - q.xg[j]);
     q.v[lane] = 2.0 * s;
   }
-  pf.store(q.AB[(T - 1) & 1]);
+  pf.store(q.ab(T - 1));
   wave_sync();
   add_state_terms<NX, NU, F>(I, q, fl, rho);
   wave_sync();
+  // no vector-memory load is outstanding when the stage loop starts: the
+  // compiler then tracks only the loads the loop issues itself, and the loads
+  // of the next stage stay in flight while the current one is computed
+  // (immediate: vmcnt 0, expcnt and lgkmcnt unconstrained)
+  __builtin_amdgcn_s_waitcnt(0x0F70);
   for (int k = T - 1; k >= 0; --k) {
-    const double* A = q.AB[k & 1];
+    const double* A = q.ab(k);
     const double* B = A + NX * NX;
     const double* xk = B + NX * NU;
     const double* uk = xk + NX;
     fl = fln;
     if (k > 0) {
       stage_load(k - 1);
-      fln.load(I, tls, tlc, k - 1, k - 1);
+      fln.load(bact, bbeta, bcm, tls, tlc, k - 1, k - 1);
     }
+#pragma unroll 1
     for (int idx = lane; idx < NX * NX; idx += NRTO_WAVE) {
       const int i = idx / NX, j = idx - i * NX;
       double s = 0.0;
@@ -1261,6 +1403,7 @@ __device__ void riccati(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double r
       for (int l = 0; l < NX; ++l) s += q.V[i * NX + l] * A[l * NX + j];
       q.PA[idx] = s;
     }
+#pragma unroll 1
     for (int idx = lane; idx < NX * NU; idx += NRTO_WAVE) {
       const int i = idx / NU, u = idx - i * NU;
       double s = 0.0;
@@ -1269,6 +1412,7 @@ __device__ void riccati(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double r
       q.PB[idx] = s;
     }
     wave_sync();
+#pragma unroll 1
     for (int idx = lane; idx < NU * NU; idx += NRTO_WAVE) {
       const int u = idx / NU, w = idx - u * NU;
       double s = 2.0 * q.Rs[idx];
@@ -1276,6 +1420,7 @@ __device__ void riccati(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double r
       for (int i = 0; i < NX; ++i) s += B[i * NU + u] * q.PB[i * NU + w];
       q.Huu[idx] = s;
     }
+#pragma unroll 1
     for (int idx = lane; idx < NU * NX; idx += NRTO_WAVE) {
       const int u = idx / NX, j = idx - u * NX;
       double s = 0.0;
@@ -1303,12 +1448,12 @@ __device__ void riccati(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double r
       for (int i = 0; i < NU * NU; ++i) Hl[i] = q.Huu[i];
 #pragma unroll
       for (int u = 0; u < NU; ++u) hl[u] = q.hu[u];
-      uint64_t cmask = __ballot(fl.cf);
+      uint64_t cmask = __ballot(fl.cf());
       while (cmask) {
         const int bit = __ffsll((unsigned long long)cmask) - 1;
         cmask &= cmask - 1;
         const int ci = __shfl(fl.ccidx, bit, NRTO_WAVE);
-        const double hb = __shfl(fl.cbs, bit, NRTO_WAVE);
+        const double hb = __shfl(fl.cbs(), bit, NRTO_WAVE);
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
           if (u == ci) {
@@ -1330,7 +1475,6 @@ __device__ void riccati(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double r
         }
       }
       chol_inplace<NU>(Hl);
-      double* gk = I.ric + (int64_t)k * NU * (NX + 1);
       if (lane <= NX) {
         double z[NU];
 #pragma unroll
@@ -1338,7 +1482,8 @@ __device__ void riccati(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double r
         chol_solve<NU>(Hl, z);
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
-          gk[u * (NX + 1) + lane] = -z[u];
+          if (lane < NX) q.gfb[(k * NU + u) * NX + lane] = -z[u];
+          else q.gff[k * NU + u] = -z[u];
           q.G[u * (NX + 1) + lane] = -z[u];
         }
       }
@@ -1348,10 +1493,15 @@ __device__ void riccati(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double r
       // cost-to-go of stage k: V = 2Q + mu I + A'(V A) + H_ux' G_x is symmetric;
       // its upper triangle is computed and written to both halves
       constexpr int NTRI = NX * (NX + 1) / 2;
-      double nv[(NTRI + NRTO_WAVE - 1) / NRTO_WAVE];
-      int ti[(NTRI + NRTO_WAVE - 1) / NRTO_WAVE], tj[(NTRI + NRTO_WAVE - 1) / NRTO_WAVE];
-      int n = 0;
-      for (int idx = lane; idx < NTRI; idx += NRTO_WAVE, ++n) {
+      constexpr int NPER = (NTRI + NRTO_WAVE - 1) / NRTO_WAVE;
+      double nv[NPER];
+      int ti[NPER], tj[NPER];
+#pragma unroll
+      for (int n = 0; n < NPER; ++n) {
+        const int idx = lane + n * NRTO_WAVE;
+        nv[n] = 0.0;
+        ti[n] = tj[n] = 0;
+        if (idx >= NTRI) continue;
         int i = 0, rem = idx;   // row i of the upper triangle holds NX - i entries
         while (rem >= NX - i) {
           rem -= NX - i;
@@ -1379,42 +1529,41 @@ __device__ void riccati(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double r
         vv = sum;
       }
       // V, v are not read by the products above (only V A, H_ux and G): update in place
-      n = 0;
-      for (int idx = lane; idx < NTRI; idx += NRTO_WAVE, ++n) {
+#pragma unroll
+      for (int n = 0; n < NPER; ++n) {
+        if (lane + n * NRTO_WAVE >= NTRI) continue;
         q.V[ti[n] * NX + tj[n]] = nv[n];
         q.V[tj[n] * NX + ti[n]] = nv[n];
       }
       wave_sync();
       if (lane < NX) q.v[lane] = vv;
-      pf.store(q.AB[(k - 1) & 1]);
+      pf.store(q.ab(k - 1));
       wave_sync();
       add_state_terms<NX, NU, F>(I, q, fl, rho);
       wave_sync();
     }
   }
-  // forward rollout from dx_0 = 0: the stage's A, B and gains are staged in LDS
-  // one stage ahead; the current state and control stay in LDS (q.tmp), their
-  // global copies are only written
+  // forward rollout from dx_0 = 0: the stage's A, B are staged in LDS one stage
+  // ahead, the gains are read from LDS; the current state and control stay in
+  // LDS (q.tmp), their global copies are only written
   FwdPrefetch<NX, NU> fp;
-  auto fwd_load = [&](int k) {
-    fp.load(I.A + (int64_t)k * NX * NX, I.B + (int64_t)k * NX * NU, I.ric + (int64_t)k * NU * (NX + 1));
-  };
+  auto fwd_load = [&](int k) { fp.load(bA, bB, k); };
   if (lane < NX) {
     q.tmp[lane] = 0.0;
     I.dx2[lane] = 0.0;
   }
   fwd_load(0);
-  fp.store(q.AB[0]);
+  fp.store(q.ab(0));
   wave_sync();
   for (int k = 0; k < T; ++k) {
-    const double* A = q.AB[k & 1];
+    const double* A = q.ab(k);
     const double* B = A + NX * NX;
-    const double* gk = B + NX * NU;
     if (k + 1 < T) fwd_load(k + 1);
     if (lane < NU) {
-      double s = gk[lane * (NX + 1) + NX];
+      const double* gx = q.gfb + (k * NU + lane) * NX;
+      double s = q.gff[k * NU + lane];
 #pragma unroll
-      for (int j = 0; j < NX; ++j) s += gk[lane * (NX + 1) + j] * q.tmp[j];
+      for (int j = 0; j < NX; ++j) s += gx[j] * q.tmp[j];
       q.tmp[NX + lane] = s;
       I.du2[k * NU + lane] = s;
     }
@@ -1433,7 +1582,7 @@ __device__ void riccati(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double r
       q.tmp[lane] = xn;
       I.dx2[(k + 1) * NX + lane] = xn;
     }
-    if (k + 1 < T) fp.store(q.AB[(k + 1) & 1]);
+    if (k + 1 < T) fp.store(q.ab(k + 1));
     wave_sync();
   }
 }
@@ -1616,9 +1765,12 @@ __device__ void rollout_dx(const Inst<NX, NU, F>& I) {
 }
 
 template <int NX, int NU, typename F>
-__device__ __noinline__ int qp_block(const Inst<NX, NU, F> I, QPScratch<NX, NU> q, double rho) {
-  // compiled out of line with its instance view and LDS carve-up by value: the
-  // pointers live in registers and carry their address spaces
+__device__ __noinline__ int qp_block(const Inst<NX, NU, F> Iarg, QPScratch<NX, NU> qarg, double rho) {
+  // compiled out of line with its instance view and LDS carve-up by value; the
+  // pointers carry their address spaces and are made wave-uniform (scalar
+  // registers) on entry
+  const Inst<NX, NU, F> I = uniform_inst(Iarg);
+  QPScratch<NX, NU> q = qp_carve<NX, NU>(uni(qarg.V), uni(qarg.gfb), uni(qarg.gff));
   // Trust-region multiplier: mu = 0 if psi(0) = ||F_u du(0)|| <= r, else the
   // root of phi(mu) = 1/r - 1/psi(mu), which increases with mu and is close to
   // linear in it (exactly so when F_u'F_u acts on one eigen-direction of the
@@ -1849,7 +2001,7 @@ __device__ double kkt_residual(const Inst<NX, NU, F>& I, Smem<F>& S, const Solve
   // T1 by costate recursions on wave 0
   double t1v = 0.0;
   if (wave_id() == 0) {
-    QPScratch<NX, NU> q = qp_carve<NX, NU>(S.qp);
+    QPScratch<NX, NU> q = qp_carve<NX, NU>(S.qp, S.gfb, S.gff);
     const int lane = lane_id();
     // lanes 0..NX-1: cost costate; NX..2NX-1: pi costate; 2NX..3NX-1: trust costate
     const int which = lane / NX, i = lane - which * NX;
@@ -2142,7 +2294,7 @@ __device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, L<c
     }
     // (du, p) block on wave 0
     if (wave_id() == 0) {
-      QPScratch<NX, NU> q = qp_carve<NX, NU>(S.qp);
+      QPScratch<NX, NU> q = qp_carve<NX, NU>(S.qp, S.gfb, S.gff);
       const int n = qp_block<NX, NU, F>(I, q, rho);
       if (lane_id() == 0) S.red[65] = (double)n;
     }
