@@ -200,11 +200,11 @@ static nrto_status build_instance(nrto_ctx c, const nrto_problem& p, HostInst& h
     while (j < ng) {
       int len = 1 + cm[j * CM_N + CM_NBLK] * nx;
       if (len > 64) {
-        longt.push_back({j, 1, cm[j * CM_N + CM_EOFF], len});
+        longt.push_back({j, 1, cm[j * CM_N + CM_EOFF], len, cm[j * CM_N + CM_K0], cm[j * CM_N + CM_BOFF], 0, 0});
         ++j;
         continue;
       }
-      WaveTask tk{j, 0, cm[j * CM_N + CM_EOFF], 0};
+      WaveTask tk{j, 0, cm[j * CM_N + CM_EOFF], 0, 0, 0, 0, 0};
       uint64_t mask = 0;
       while (j < ng) {
         int l2 = 1 + cm[j * CM_N + CM_NBLK] * nx;

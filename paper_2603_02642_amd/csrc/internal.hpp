@@ -96,6 +96,9 @@ struct WaveTask {
   int32_t ncone;
   int32_t ebeg;    // first entry (local index)
   int32_t len;     // entries
+  int32_t k0;      // single-cone task: the cone's first block and first block
+  int32_t boff;    // vector (its metadata, so that one load describes the task)
+  int32_t pad0, pad1;
 };
 
 enum { ISCR_PSI = 0, ISCR_KKT, ISCR_RP, ISCR_RD, ISCR_MUHINT, ISCR_N = 8 };

@@ -67,6 +67,7 @@ struct Smem {
   L<double>* red;  // 128: [0, 64) block reductions, [64, 128) broadcast scalars
   L<double>* wscr; // W*128: per-wave cone sums / broadcast
   L<double>* qp;   // wave-0 QP scratch
+  L<F>* bl;        // DR pass: per-wave block-vector slices, (T+1)*NU each (the LDS of qp, idle then)
   L<double>* gfb;  // Riccati feedback gains, T*NU*NX: [k][u][x] (the LDS of Kf when F is double)
   L<double>* gff;  // Riccati feedforward gains, T*NU: [k][u]
   L<int>* ctr;     // 4 ints
@@ -79,6 +80,13 @@ __host__ __device__ inline size_t qp_scratch_doubles(int nx, int nu) {
          2 * (nx * nx + nx * nu + nu * (nx + 1)) + nu * (nx + 1) + nx * nx + nu * nu + nx + 160 + (2 * MAX_T + 4) / 2;
 }
 
+// The QP scratch block also holds the DR pass's per-wave block-vector slices.
+__host__ __device__ inline size_t qp_region_bytes(int T, int nx, int nu, int fbytes, int W) {
+  const size_t q = qp_scratch_doubles(nx, nu) * 8;
+  const size_t b = (size_t)W * (T + 1) * nu * fbytes;
+  return align16(q > b ? q : b);
+}
+
 __host__ __device__ inline size_t smem_bytes(int T, int nx, int nu, int fbytes, int W) {
   size_t s = 0;
   s += align16((size_t)nu * T * nx * fbytes);
@@ -86,7 +94,7 @@ __host__ __device__ inline size_t smem_bytes(int T, int nx, int nu, int fbytes, 
   s += align16((size_t)T * nu * nu * 8);
   s += align16(128 * 8);
   s += align16((size_t)W * 128 * 8);
-  s += align16(qp_scratch_doubles(nx, nu) * 8);
+  s += qp_region_bytes(T, nx, nu, fbytes, W);
   s += align16((size_t)T * nu * 8);                  // feedforward gains
   if (fbytes < 8) s += align16((size_t)T * nu * nx * 8);   // feedback gains (else in Kf's LDS)
   s += 16;
@@ -102,7 +110,8 @@ __device__ Smem<F> carve(L<char>* base, int T, int nx, int nu, int W) {
   m.Gl = (L<double>*)(base + o); o += align16((size_t)T * nu * nu * 8);
   m.red = (L<double>*)(base + o); o += align16(128 * 8);
   m.wscr = (L<double>*)(base + o); o += align16((size_t)W * 128 * 8);
-  m.qp = (L<double>*)(base + o); o += align16(qp_scratch_doubles(nx, nu) * 8);
+  m.qp = (L<double>*)(base + o); o += qp_region_bytes(T, nx, nu, (int)sizeof(F), W);
+  m.bl = (L<F>*)m.qp;
   m.gff = (L<double>*)(base + o); o += align16((size_t)T * nu * 8);
   if (sizeof(F) < 8) {
     m.gfb = (L<double>*)(base + o);
@@ -537,46 +546,108 @@ __device__ __forceinline__ void soc_case(double t, double a, double& that, doubl
 // DR pass: one relaxed DR iteration over all cones of the instance (after the
 // K-solve).  Accumulates sum ||delta s~||^2 and ||s~||^2.
 //
-// A long cone (65..64*E entries) is handled by one wave in a single sweep: every
-// lane first issues the loads of its E entries of s~ and b_hat (independent, so
-// they are in flight together), then forms eta(K) with the block vectors and
-// K_k from LDS, reduces the reflected norm, and projects / relaxes / stores the
-// entries it holds in registers.  The cone's metadata is read once per cone.
+// A long cone (more than 64 entries) is handled by one wave.  The wave first
+// copies the cone's block vectors b_{j,k} (at most (T+1)*NU values) into its
+// LDS slice, and every lane issues the loads of its entries of s~ and b_hat
+// (independent, so they are in flight together with the block vectors).  It
+// then forms eta(K) from the block vectors and K_k in LDS, reduces the
+// reflected norm, and projects / relaxes / stores its entries.  Up to 64*E
+// entries a lane keeps s~, b_hat and eta of its E entries in registers (one
+// sweep over the cone's data); longer cones take two sweeps (the second reloads
+// s~ and b_hat).  The cone's first block, first block vector and multiplier
+// data come with the task.
 #ifndef NRTO_DR_STAGE
-#define NRTO_DR_STAGE 4
+#define NRTO_DR_STAGE 8
 #endif
-constexpr int DR_STAGE = NRTO_DR_STAGE;   // chunks of 64 entries a lane holds per sweep
+constexpr int DR_STAGE = NRTO_DR_STAGE;   // chunks of 64 entries a lane holds in one sweep
 
+// The cone's multiplier data (cd: p~~, p, lambda of the cone, loaded with the
+// cone's entries) enter the t slot: p~ = (sigma_chi p~~ + rho p + lambda +
+// sigma_s s~_0) / den.
+struct ConeDual {
+  double ptt, p, lam;
+};
+
+// Copy of a cone's n block-vector values into the wave's LDS slice, 4*64 values
+// a round: load() issues a round's loads, store() writes them to LDS.  The
+// first round is loaded before the cone's entries and stored after them (the
+// store then waits for these loads only: vector-memory loads complete in
+// order); cones with more than 256 values (long horizons) take further rounds.
+template <typename F>
+struct BlockStage {
+  static constexpr int PL = 4;
+  F v[PL];
+  __device__ void load(const G<F>* __restrict__ bv, int n, int base) {
+#pragma unroll
+    for (int i = 0; i < PL; ++i) {
+      const int idx = base + lane_id() + i * NRTO_WAVE;
+      v[i] = (idx < n) ? bv[idx] : (F)0;
+    }
+  }
+  __device__ void store(F* bl, int n, int base) const {
+#pragma unroll
+    for (int i = 0; i < PL; ++i) {
+      const int idx = base + lane_id() + i * NRTO_WAVE;
+      if (idx < n) bl[idx] = v[i];
+    }
+  }
+  // the rounds after the first
+  __device__ void rest(const G<F>* __restrict__ bv, int n, F* bl) {
+    for (int base = PL * NRTO_WAVE; base < n; base += PL * NRTO_WAVE) {
+      load(bv, n, base);
+      store(bl, n, base);
+    }
+  }
+};
+
+// eta entry (before the reflection) of entry le >= 1 of a cone starting at block k0:
+// r * b_{j,k}' K_k[:, x] + b_hat (a block at k = T, the terminal block of a state
+// constraint, carries no gain).
+template <int NX, int NU, typename F>
+__device__ __forceinline__ F cone_eta(const F* bl, const F* Kf, int T, int k0, int le, F r, F bh, int& k, int& x,
+                                      int& blk) {
+  const int q = le - 1;
+  blk = q / NX;
+  x = q - blk * NX;
+  k = k0 + blk;
+  F f = (F)0;
+  if (k < T) {
+#pragma unroll
+    for (int u = 0; u < NU; ++u) f += bl[blk * NU + u] * Kf[(u * T + k) * NX + x];
+  }
+  return r * f + bh;
+}
+
+template <int NX, int NU, typename F>
+__device__ __forceinline__ void cone_adjoint(const F* bl, F* Racc, int T, int k, int x, int blk, F d) {
+  if (k >= T) return;
+#pragma unroll
+  for (int u = 0; u < NU; ++u) atomicAdd(&Racc[(u * T + k) * NX + x], bl[blk * NU + u] * d);
+}
+
+// One sweep: a cone of at most 64*E entries.
 template <int NX, int NU, typename F, int E>
-__device__ __forceinline__ void dr_long_cone(const WaveTask tk, const G<int32_t>* __restrict__ m,
-                                             G<F>* __restrict__ st, const G<F>* __restrict__ bhat,
-                                             const G<F>* __restrict__ bvec, const F* Kf, F* Racc, int T, F r,
-                                             double al, double ptc_num, double sig, double den,
-                                             G<double>* ca_pt, G<double>* ca_ptt, double (&acc)[5]) {
+__device__ __forceinline__ void dr_long_cone(const WaveTask tk, G<F>* __restrict__ st, const G<F>* __restrict__ bhat,
+                                             const G<F>* __restrict__ bvec, const F* Kf, F* Racc, F* bl, int T, F r,
+                                             double al, const ConeDual cd, double chi, double rho, double sig,
+                                             double den, G<double>* ca_pt, G<double>* ca_ptt, double (&acc)[5]) {
   const int lane = lane_id();
   const int len = tk.len;
-  const int k0 = m[CM_K0], boff = m[CM_BOFF];
-  // every load of the cone first: s~, b_hat and the block vector of each entry
-  // (a state constraint at t = T stores a zero block T, so the block vector of
-  // every entry exists)
-  F stv[E], bhv[E], bvr[E][NU];
+  const int k0 = tk.k0;
+  const G<F>* bvp = bvec + (int64_t)tk.boff * NU;
+  const int nbv = ((len - 1) / NX) * NU;
+  BlockStage<F> bs;
+  bs.load(bvp, nbv, 0);
+  F stv[E], bhv[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int le = lane + i * NRTO_WAVE;
-    stv[i] = (F)0;
-    bhv[i] = (F)0;
-#pragma unroll
-    for (int u = 0; u < NU; ++u) bvr[i][u] = (F)0;
-    if (le < len) {
-      stv[i] = st[le];
-      if (le >= 1) {
-        bhv[i] = bhat[le];
-        const G<F>* bv = bvec + (int64_t)(boff + (le - 1) / NX) * NU;
-#pragma unroll
-        for (int u = 0; u < NU; ++u) bvr[i][u] = bv[u];
-      }
-    }
+    stv[i] = (le < len) ? st[le] : (F)0;
+    bhv[i] = (le >= 1 && le < len) ? bhat[le] : (F)0;
   }
+  bs.store(bl, nbv, 0);
+  bs.rest(bvp, nbv, bl);
+  wave_sync();   // the block vectors in LDS
   // forward gain GEMM and the norm of the reflected eta
   F sv[E];
   double sq = 0.0;
@@ -585,23 +656,15 @@ __device__ __forceinline__ void dr_long_cone(const WaveTask tk, const G<int32_t>
     const int le = lane + i * NRTO_WAVE;
     sv[i] = (F)0;
     if (le >= 1 && le < len) {
-      const int q = le - 1;
-      const int blk = q / NX;
-      const int x = q - blk * NX;
-      const int k = k0 + blk;
-      F f = (F)0;
-      if (k < T) {   // the last block of a state constraint at t = T has no gain
-#pragma unroll
-        for (int u = 0; u < NU; ++u) f += bvr[i][u] * Kf[(u * T + k) * NX + x];
-      }
-      sv[i] = r * f + bhv[i];
+      int k, x, blk;
+      sv[i] = cone_eta<NX, NU, F>(bl, Kf, T, k0, le, r, bhv[i], k, x, blk);
       const F sr = (F)2 * sv[i] - stv[i];
       sq += (double)sr * (double)sr;
     }
   }
   double ptc = 0.0, tr0 = 0.0;
   if (lane == 0) {
-    ptc = (ptc_num + sig * (double)stv[0]) / den;
+    ptc = (chi * cd.ptt + rho * cd.p + cd.lam + sig * (double)stv[0]) / den;
     tr0 = (double)((F)2 * (F)ptc - stv[0]);
   }
   const double a = sqrt(wave_sum(sq));
@@ -630,78 +693,67 @@ __device__ __forceinline__ void dr_long_cone(const WaveTask tk, const G<int32_t>
       nsum += (double)stn * (double)stn;
       ssum += (double)s * (double)s;
       if (le > 0) {
-        const int q = le - 1;
-        const int blk = q / NX;
-        const int x = q - blk * NX;
-        const int k = k0 + blk;
-        if (k < T) {
-          const F d = stn - bhv[i];
-#pragma unroll
-          for (int u = 0; u < NU; ++u) atomicAdd(&Racc[(u * T + k) * NX + x], bvr[i][u] * d);
-        }
+        const int q = le - 1, blk = q / NX, x = q - blk * NX;
+        cone_adjoint<NX, NU, F>(bl, Racc, T, k0 + blk, x, blk, stn - bhv[i]);
       }
     }
   }
   if (lane == 0) {
     *ca_pt = ptc;
-    const double pt0 = *ca_ptt;
-    *ca_ptt = pt0 + al * (ptc - pt0);
+    *ca_ptt = cd.ptt + al * (ptc - cd.ptt);
   }
   acc[0] += dsum;
   acc[1] += nsum;
   acc[4] += ssum;
+  wave_sync();   // the slice is reused by the wave's next cone
 }
 
-// Cones longer than one register-staged sweep holds: two sweeps over the
-// entries in groups of E chunks (the first forms the reflected norm, the
-// second reloads the group, recomputes eta, projects, relaxes and accumulates
-// the adjoint); the loads of a group are issued together.
+// Cones longer than one sweep holds: two sweeps over the entries in groups of
+// E chunks (the first forms the reflected norm, the second reloads the group,
+// recomputes eta, projects, relaxes and accumulates the adjoint).
 template <int NX, int NU, typename F, int E>
-__device__ __forceinline__ void dr_long_cone_2pass(const WaveTask tk, const G<int32_t>* __restrict__ m,
-                                                   G<F>* __restrict__ st, const G<F>* __restrict__ bhat,
-                                                   const G<F>* __restrict__ bvec, const F* Kf, F* Racc, int T, F r,
-                                                   double al, double ptc_num, double sig, double den,
+__device__ __forceinline__ void dr_long_cone_2pass(const WaveTask tk, G<F>* __restrict__ st,
+                                                   const G<F>* __restrict__ bhat, const G<F>* __restrict__ bvec,
+                                                   const F* Kf, F* Racc, F* bl, int T, F r, double al,
+                                                   const ConeDual cd, double chi, double rho, double sig, double den,
                                                    G<double>* ca_pt, G<double>* ca_ptt, double (&acc)[5]) {
   const int lane = lane_id();
   const int len = tk.len;
-  const int k0 = m[CM_K0], boff = m[CM_BOFF];
-  double sq = 0.0, ptc = 0.0, tr0 = 0.0;
-  if (lane == 0) {
-    const F st0 = st[0];
-    ptc = (ptc_num + sig * (double)st0) / den;
-    tr0 = (double)((F)2 * (F)ptc - st0);
-  }
+  const int k0 = tk.k0;
+  const G<F>* bvp = bvec + (int64_t)tk.boff * NU;
+  const int nbv = ((len - 1) / NX) * NU;
+  BlockStage<F> bs;
+  bs.load(bvp, nbv, 0);
+  const F st0 = (lane == 0) ? st[0] : (F)0;   // used after the first sweep
+  double sq = 0.0;
   for (int base = 0; base < len; base += E * NRTO_WAVE) {
-    F stv[E], bhv[E], bvr[E][NU];
+    F stv[E], bhv[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const int le = base + lane + i * NRTO_WAVE;
-      stv[i] = (F)0;
-      bhv[i] = (F)0;
-#pragma unroll
-      for (int u = 0; u < NU; ++u) bvr[i][u] = (F)0;
-      if (le >= 1 && le < len) {
-        stv[i] = st[le];
-        bhv[i] = bhat[le];
-        const G<F>* bv = bvec + (int64_t)(boff + (le - 1) / NX) * NU;
-#pragma unroll
-        for (int u = 0; u < NU; ++u) bvr[i][u] = bv[u];
-      }
+      const bool in = le >= 1 && le < len;
+      stv[i] = in ? st[le] : (F)0;
+      bhv[i] = in ? bhat[le] : (F)0;
     }
+    if (base == 0) {
+      bs.store(bl, nbv, 0);
+      bs.rest(bvp, nbv, bl);
+    }
+    wave_sync();   // the block vectors in LDS
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const int le = base + lane + i * NRTO_WAVE;
       if (le >= 1 && le < len) {
-        const int q = le - 1, blk = q / NX, x = q - blk * NX, k = k0 + blk;
-        F f = (F)0;
-        if (k < T) {
-#pragma unroll
-          for (int u = 0; u < NU; ++u) f += bvr[i][u] * Kf[(u * T + k) * NX + x];
-        }
-        const F sr = (F)2 * (r * f + bhv[i]) - stv[i];
+        int k, x, blk;
+        const F sr = (F)2 * cone_eta<NX, NU, F>(bl, Kf, T, k0, le, r, bhv[i], k, x, blk) - stv[i];
         sq += (double)sr * (double)sr;
       }
     }
+  }
+  double ptc = 0.0, tr0 = 0.0;
+  if (lane == 0) {
+    ptc = (chi * cd.ptt + rho * cd.p + cd.lam + sig * (double)st0) / den;
+    tr0 = (double)((F)2 * (F)ptc - st0);
   }
   const double a = sqrt(wave_sum(sq));
   const double tref = __shfl(tr0, 0, NRTO_WAVE);
@@ -709,44 +761,24 @@ __device__ __forceinline__ void dr_long_cone_2pass(const WaveTask tk, const G<in
   soc_case(tref, a, that, scale);
   double dsum = 0.0, nsum = 0.0, ssum = 0.0;
   for (int base = 0; base < len; base += E * NRTO_WAVE) {
-    F stv[E], bhv[E], bvr[E][NU];
+    F stv[E], bhv[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const int le = base + lane + i * NRTO_WAVE;
-      stv[i] = (F)0;
-      bhv[i] = (F)0;
-#pragma unroll
-      for (int u = 0; u < NU; ++u) bvr[i][u] = (F)0;
-      if (le < len) {
-        stv[i] = st[le];
-        if (le >= 1) {
-          bhv[i] = bhat[le];
-          const G<F>* bv = bvec + (int64_t)(boff + (le - 1) / NX) * NU;
-#pragma unroll
-          for (int u = 0; u < NU; ++u) bvr[i][u] = bv[u];
-        }
-      }
+      stv[i] = (le < len) ? st[le] : (F)0;
+      bhv[i] = (le >= 1 && le < len) ? bhat[le] : (F)0;
     }
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const int le = base + lane + i * NRTO_WAVE;
       if (le < len) {
         F s, shat;
-        int k = 0, x = 0;
+        int k = 0, x = 0, blk = 0;
         if (le == 0) {
           s = (F)ptc;
           shat = (F)that;
         } else {
-          const int q = le - 1;
-          const int blk = q / NX;
-          x = q - blk * NX;
-          k = k0 + blk;
-          F f = (F)0;
-          if (k < T) {
-#pragma unroll
-            for (int u = 0; u < NU; ++u) f += bvr[i][u] * Kf[(u * T + k) * NX + x];
-          }
-          s = r * f + bhv[i];
+          s = cone_eta<NX, NU, F>(bl, Kf, T, k0, le, r, bhv[i], k, x, blk);
           shat = (F)(scale * (double)((F)2 * s - stv[i]));
         }
         const F diff = shat - s;
@@ -756,22 +788,18 @@ __device__ __forceinline__ void dr_long_cone_2pass(const WaveTask tk, const G<in
         dsum += dd * dd;
         nsum += (double)stn * (double)stn;
         ssum += (double)s * (double)s;
-        if (le > 0 && k < T) {
-          const F d = stn - bhv[i];
-#pragma unroll
-          for (int u = 0; u < NU; ++u) atomicAdd(&Racc[(u * T + k) * NX + x], bvr[i][u] * d);
-        }
+        if (le > 0) cone_adjoint<NX, NU, F>(bl, Racc, T, k, x, blk, stn - bhv[i]);
       }
     }
   }
   if (lane == 0) {
     *ca_pt = ptc;
-    const double pt0 = *ca_ptt;
-    *ca_ptt = pt0 + al * (ptc - pt0);
+    *ca_ptt = cd.ptt + al * (ptc - cd.ptt);
   }
   acc[0] += dsum;
   acc[1] += nsum;
   acc[4] += ssum;
+  wave_sync();   // the slice is reused by the wave's next cone
 }
 
 // Arguments of the DR pass, passed by value to a separately compiled function
@@ -788,6 +816,7 @@ struct DrArgs {
   const F* bvec;
   const F* Kf;
   F* Racc;
+  F* bl;               // per-wave block-vector slices
   double* wscr;
   int* ctr;
   int64_t lds_ctr_off;   // byte offset of ctr in the dynamic LDS
@@ -814,6 +843,7 @@ __device__ __noinline__ Acc5 dr_pass_impl(DrArgs<F> g) {
     const char* base = (const char*)g.ctr - g.lds_ctr_off;
     g.Kf = as_lds<F>(g.Kf, base);
     g.Racc = as_lds<F>(g.Racc, base);
+    g.bl = as_lds<F>(g.bl, base);
     g.wscr = as_lds<double>(g.wscr, base);
     g.ctr = as_lds<int>(g.ctr, base);
   }
@@ -833,33 +863,55 @@ __device__ __noinline__ Acc5 dr_pass_impl(DrArgs<F> g) {
   const double den = g.rho + g.sigma_chi + g.sig;
   const double rho = g.rho, sig = g.sig;
   double* ws = g.wscr + wave_id() * 128;
+  F* bl = g.bl + wave_id() * (T + 1) * NU;
   auto C = [&](int col, int j) -> G<double>& { return ca[(int64_t)col * g.cstride + j]; };
-  for (int t = next_task(g.ctr); t < g.ntask; t = next_task(g.ctr)) {
-    WaveTask tk;
-    tk.cone = tasks[t].cone;
-    tk.ncone = tasks[t].ncone;
-    tk.ebeg = tasks[t].ebeg;
-    tk.len = tasks[t].len;
+  // Static schedule: wave w takes tasks w, w + W, w + 2W, ... of the list (long
+  // cones first, by decreasing length).  A wave's next task is known in
+  // advance, so its descriptor is loaded while the current task is processed;
+  // a long cone's first block and block-vector offset come with the
+  // descriptor, and its multiplier data are loaded with its entries.
+  const int W = (int)(blockDim.x / NRTO_WAVE);
+  auto load_task = [&](int t, WaveTask& k, uint64_t& mask) {
+    const G<WaveTask>* p = tasks + t;
+    k.cone = p->cone;
+    k.ncone = p->ncone;
+    k.ebeg = p->ebeg;
+    k.len = p->len;
+    k.k0 = p->k0;
+    k.boff = p->boff;
+    mask = tmask[t];
+  };
+  int t = uni((int)wave_id());
+  WaveTask tk = {0, 0, 0, 0, 0, 0, 0, 0};
+  uint64_t tkmask = 0;
+  if (t < g.ntask) load_task(t, tk, tkmask);
+  for (; t < g.ntask; t += W) {
+    WaveTask tkn = tk;
+    uint64_t tknmask = 0;
+    if (t + W < g.ntask) load_task(t + W, tkn, tknmask);
     if (tk.ncone == 1 && tk.len > NRTO_WAVE) {
       const int c = tk.cone;
-      const G<int32_t>* m = cmeta + c * CM_N;
-      const double ptc_num = g.sigma_chi * C(CA_PTT, c) + rho * C(CA_P, c) + C(CA_LAM, c);
+      const ConeDual cd = {C(CA_PTT, c), C(CA_P, c), C(CA_LAM, c)};
       G<F>* st = gst + tk.ebeg;
       const G<F>* bh = gbhat + tk.ebeg;
       G<double>* cpt = &C(CA_PT, c);
       G<double>* cptt = &C(CA_PTT, c);
       if (tk.len <= 2 * NRTO_WAVE)
-        dr_long_cone<NX, NU, F, 2>(tk, m, st, bh, gbvec, g.Kf, g.Racc, T, r, al, ptc_num, sig, den, cpt, cptt, acc);
+        dr_long_cone<NX, NU, F, 2>(tk, st, bh, gbvec, g.Kf, g.Racc, bl, T, r, al, cd, g.sigma_chi, rho, sig, den,
+                                   cpt, cptt, acc);
+      else if (tk.len <= 4 * NRTO_WAVE)
+        dr_long_cone<NX, NU, F, 4>(tk, st, bh, gbvec, g.Kf, g.Racc, bl, T, r, al, cd, g.sigma_chi, rho, sig, den,
+                                   cpt, cptt, acc);
       else if (tk.len <= DR_STAGE * NRTO_WAVE)
-        dr_long_cone<NX, NU, F, DR_STAGE>(tk, m, st, bh, gbvec, g.Kf, g.Racc, T, r, al, ptc_num, sig, den, cpt,
-                                          cptt, acc);
+        dr_long_cone<NX, NU, F, DR_STAGE>(tk, st, bh, gbvec, g.Kf, g.Racc, bl, T, r, al, cd, g.sigma_chi, rho, sig,
+                                          den, cpt, cptt, acc);
       else
-        dr_long_cone_2pass<NX, NU, F, DR_STAGE>(tk, m, st, bh, gbvec, g.Kf, g.Racc, T, r, al, ptc_num, sig, den,
-                                                cpt, cptt, acc);
+        dr_long_cone_2pass<NX, NU, F, DR_STAGE>(tk, st, bh, gbvec, g.Kf, g.Racc, bl, T, r, al, cd, g.sigma_chi,
+                                                rho, sig, den, cpt, cptt, acc);
     } else {
       // packed short cones: one entry per lane; each lane reads its cone's
       // metadata and its block vector once
-      const uint64_t mask = tmask[t];
+      const uint64_t mask = tkmask;
       const int l = lane;
       const bool valid = l < tk.len;
       const uint64_t pre = mask & ((l == 63) ? ~0ull : ((2ull << l) - 1ull));
@@ -935,6 +987,8 @@ __device__ __noinline__ Acc5 dr_pass_impl(DrArgs<F> g) {
       }
       wave_sync();
     }
+    tk = tkn;
+    tkmask = tknmask;
   }
 #pragma unroll
   for (int i = 0; i < 5; ++i) out.v[i] = acc[i];
@@ -955,6 +1009,7 @@ __device__ __forceinline__ void dr_pass(const Inst<NX, NU, F>& I, Smem<F>& S, co
   g.bvec = I.bvec;
   g.Kf = S.Kf;
   g.Racc = S.Racc;
+  g.bl = S.bl;
   g.wscr = S.wscr;
   g.ctr = S.ctr;
   g.lds_ctr_off = (int64_t)((const char*)S.ctr - (const char*)nrto_dyn_smem);
