@@ -168,24 +168,27 @@ __device__ void block_max(double* red, double (&v)[NV], int W) {
 
 template <int NU>
 __device__ __forceinline__ void chol_inplace(double* G) {
-  // lower Cholesky of an NU x NU SPD matrix stored row-major; upper part untouched
+  // lower Cholesky factor L of an NU x NU SPD matrix stored row-major, with
+  // 1 / L_jj stored on the diagonal (the solves multiply by it: one division
+  // per column instead of one per entry); upper part untouched
 #pragma unroll
   for (int j = 0; j < NU; ++j) {
     double s = G[j * NU + j];
 #pragma unroll
     for (int l = 0; l < j; ++l) s -= G[j * NU + l] * G[j * NU + l];
-    const double d = sqrt(fmax(s, 1e-300));
-    G[j * NU + j] = d;
+    const double rd = 1.0 / sqrt(fmax(s, 1e-300));
+    G[j * NU + j] = rd;
 #pragma unroll
     for (int i = j + 1; i < NU; ++i) {
       double t = G[i * NU + j];
 #pragma unroll
       for (int l = 0; l < j; ++l) t -= G[i * NU + l] * G[j * NU + l];
-      G[i * NU + j] = t / d;
+      G[i * NU + j] = t * rd;
     }
   }
 }
 
+// Solve (L L') z = z in place with a factor from chol_inplace.
 template <int NU>
 __device__ __forceinline__ void chol_solve(const double* L, double (&z)[NU]) {
 #pragma unroll
@@ -193,15 +196,29 @@ __device__ __forceinline__ void chol_solve(const double* L, double (&z)[NU]) {
     double t = z[i];
 #pragma unroll
     for (int l = 0; l < i; ++l) t -= L[i * NU + l] * z[l];
-    z[i] = t / L[i * NU + i];
+    z[i] = t * L[i * NU + i];
   }
 #pragma unroll
   for (int i = NU - 1; i >= 0; --i) {
     double t = z[i];
 #pragma unroll
     for (int l = i + 1; l < NU; ++l) t -= L[l * NU + i] * z[l];
-    z[i] = t / L[i * NU + i];
+    z[i] = t * L[i * NU + i];
   }
+}
+
+// One FP64 matrix-core product on a wave: D = A B + C with A 16x4, B 4x16, C and
+// D 16x16.  Lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]; register i of
+// lane l holds C[l / 16 + 4 i][l % 16], and so D.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ f64x4 mfma_f64_16x16x4(double a, double b, f64x4 c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+#else
+  (void)a;
+  (void)b;
+  return c;
+#endif
 }
 
 // ----------------------------------------------------------------------------
@@ -1397,6 +1414,10 @@ __device__ __noinline__ void riccati(const Inst<NX, NU, F> Iarg, QPScratch<NX, N
   const Inst<NX, NU, F> I = uniform_inst(Iarg);
   QPScratch<NX, NU> q = qp_carve<NX, NU>(uni(qarg.V), uni(qarg.gfb), uni(qarg.gff));   // V is the carve-up's base
   const int lane = lane_id();
+  // stage products on the matrix cores when [A | B] fits one 16-wide tile
+  constexpr int NXU = NX + NU;
+  constexpr bool MFMA_STAGE = NXU <= 16 && NU <= 4;
+  constexpr int KB = (NX + 3) / 4;   // 4-deep blocks of the contraction over n_x
   const int T = I.T;
   StagePrefetch<NX, NU> pf;
   StageFlags fl, fln;
@@ -1450,38 +1471,68 @@ __device__ __noinline__ void riccati(const Inst<NX, NU, F> Iarg, QPScratch<NX, N
       stage_load(k - 1);
       fln.load(bact, bbeta, bcm, tls, tlc, k - 1, k - 1);
     }
-#pragma unroll 1
-    for (int idx = lane; idx < NX * NX; idx += NRTO_WAVE) {
-      const int i = idx / NX, j = idx - i * NX;
-      double s = 0.0;
+    // stage products.  Matrix cores (n_x + n_u <= 16, n_u <= 4): with
+    // C = [A | B], P = V C (three 16x16x4 products for n_x = 12) and then
+    // M = C' P; register kb of P is the B operand of block kb of the second
+    // product and the A operand is C's value the lane already loaded.  M holds
+    // A'V A (kept in registers for the cost-to-go), H_ux = B'V A and B'V B.
+    [[maybe_unused]] f64x4 Mreg = {0.0, 0.0, 0.0, 0.0};
+    if constexpr (MFMA_STAGE) {
+      const int r = lane & 15, kq = lane >> 4;
+      f64x4 P = {0.0, 0.0, 0.0, 0.0};
+      double cv[KB];
 #pragma unroll
-      for (int l = 0; l < NX; ++l) s += q.V[i * NX + l] * A[l * NX + j];
-      q.PA[idx] = s;
-    }
-#pragma unroll 1
-    for (int idx = lane; idx < NX * NU; idx += NRTO_WAVE) {
-      const int i = idx / NU, u = idx - i * NU;
-      double s = 0.0;
+      for (int kb = 0; kb < KB; ++kb) {
+        const int kk = 4 * kb + kq;
+        const double va = (r < NX && kk < NX) ? q.V[r * NX + kk] : 0.0;
+        cv[kb] = (kk < NX && r < NXU) ? (r < NX ? A[kk * NX + r] : B[kk * NU + (r - NX)]) : 0.0;
+        P = mfma_f64_16x16x4(va, cv[kb], P);
+      }
 #pragma unroll
-      for (int l = 0; l < NX; ++l) s += q.V[i * NX + l] * B[l * NU + u];
-      q.PB[idx] = s;
-    }
-    wave_sync();
-#pragma unroll 1
-    for (int idx = lane; idx < NU * NU; idx += NRTO_WAVE) {
-      const int u = idx / NU, w = idx - u * NU;
-      double s = 2.0 * q.Rs[idx];
+      for (int kb = 0; kb < KB; ++kb) Mreg = mfma_f64_16x16x4(cv[kb], P[kb], Mreg);
 #pragma unroll
-      for (int i = 0; i < NX; ++i) s += B[i * NU + u] * q.PB[i * NU + w];
-      q.Huu[idx] = s;
-    }
+      for (int i = 0; i < 4; ++i) {
+        const int row = kq + 4 * i;
+        if (row >= NX && row < NXU) {
+          const int u = row - NX;
+          if (r < NX) q.Hux[u * NX + r] = Mreg[i];
+          else if (r < NXU) q.Huu[u * NU + (r - NX)] = 2.0 * q.Rs[u * NU + (r - NX)] + Mreg[i];
+        }
+      }
+    } else {
 #pragma unroll 1
-    for (int idx = lane; idx < NU * NX; idx += NRTO_WAVE) {
-      const int u = idx / NX, j = idx - u * NX;
-      double s = 0.0;
+      for (int idx = lane; idx < NX * NX; idx += NRTO_WAVE) {
+        const int i = idx / NX, j = idx - i * NX;
+        double s = 0.0;
 #pragma unroll
-      for (int i = 0; i < NX; ++i) s += B[i * NU + u] * q.PA[i * NX + j];
-      q.Hux[idx] = s;
+        for (int l = 0; l < NX; ++l) s += q.V[i * NX + l] * A[l * NX + j];
+        q.PA[idx] = s;
+      }
+#pragma unroll 1
+      for (int idx = lane; idx < NX * NU; idx += NRTO_WAVE) {
+        const int i = idx / NU, u = idx - i * NU;
+        double s = 0.0;
+#pragma unroll
+        for (int l = 0; l < NX; ++l) s += q.V[i * NX + l] * B[l * NU + u];
+        q.PB[idx] = s;
+      }
+      wave_sync();
+#pragma unroll 1
+      for (int idx = lane; idx < NU * NU; idx += NRTO_WAVE) {
+        const int u = idx / NU, w = idx - u * NU;
+        double s = 2.0 * q.Rs[idx];
+#pragma unroll
+        for (int i = 0; i < NX; ++i) s += B[i * NU + u] * q.PB[i * NU + w];
+        q.Huu[idx] = s;
+      }
+#pragma unroll 1
+      for (int idx = lane; idx < NU * NX; idx += NRTO_WAVE) {
+        const int u = idx / NX, j = idx - u * NX;
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < NX; ++i) s += B[i * NU + u] * q.PA[i * NX + j];
+        q.Hux[idx] = s;
+      }
     }
     if (lane < NU) {
       double s = 0.0;
@@ -1544,7 +1595,41 @@ __device__ __noinline__ void riccati(const Inst<NX, NU, F> Iarg, QPScratch<NX, N
       }
     }
     wave_sync();
-    if (k > 0) {
+    if (k > 0 && MFMA_STAGE) {
+      // cost-to-go of stage k: V = 2Q + mu I + A'V A + H_ux' G_x, the last term
+      // one more matrix-core product accumulated onto A'V A; the upper triangle
+      // is written to both halves (V is symmetric)
+      const int r = lane & 15, kq = lane >> 4;
+      const double ha = (kq < NU && r < NX) ? q.Hux[kq * NX + r] : 0.0;
+      const double gb = (kq < NU && r < NX) ? q.G[kq * (NX + 1) + r] : 0.0;
+      const f64x4 D = mfma_f64_16x16x4(ha, gb, Mreg);
+      double vv = 0.0;
+      if (lane < NX) {
+        double sum = 0.0;
+        for (int j = 0; j < NX; ++j) sum += q.Qs[lane * NX + j] * (xk[j] - q.xg[j]);
+        sum *= 2.0;
+#pragma unroll
+        for (int l = 0; l < NX; ++l) sum += A[l * NX + lane] * q.v[l];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) sum += q.Hux[u * NX + lane] * q.G[u * (NX + 1) + NX];
+        vv = sum;
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = kq + 4 * i;
+        if (row < NX && r < NX && row <= r) {
+          const double val = 2.0 * q.Qs[row * NX + r] + (row == r ? mu : 0.0) + D[i];
+          q.V[row * NX + r] = val;
+          q.V[r * NX + row] = val;
+        }
+      }
+      wave_sync();
+      if (lane < NX) q.v[lane] = vv;
+      pf.store(q.ab(k - 1));
+      wave_sync();
+      add_state_terms<NX, NU, F>(I, q, fl, rho);
+      wave_sync();
+    } else if (k > 0) {
       // cost-to-go of stage k: V = 2Q + mu I + A'(V A) + H_ux' G_x is symmetric;
       // its upper triangle is computed and written to both halves
       constexpr int NTRI = NX * (NX + 1) / 2;
