@@ -2040,57 +2040,133 @@ __device__ double kkt_residual(const Inst<NX, NU, F>& I, Smem<F>& S, const Solve
                                int W) {
   const int T = I.T;
   const double r = I.r;
-  // zero accumulator of sum_j A_hat_j' zeta_j
-  for (int i = threadIdx.x; i < T * NU * NX; i += blockDim.x) I.kscr[i] = 0.0;
-  if (threadIdx.x == 0) *S.ctr = 0;
-  __syncthreads();
-  // entry pass: per cone ||eta||^2, ||zeta||^2, zeta.eta ; adjoint of zeta
-  for (int t = next_task(S.ctr); t < I.ntask; t = next_task(S.ctr)) {
-    const WaveTask tk = I.tasks[t];
-    for (int c = tk.cone; c < tk.cone + tk.ncone; ++c) {
-      const int32_t* m = I.cm + c * CM_N;
-      const int e0 = m[CM_EOFF];
-      const int len = 1 + m[CM_NBLK] * NX;
-      double n2 = 0.0, z2 = 0.0, ze = 0.0;
-      for (int le = 1 + lane_id(); le < len; le += NRTO_WAVE) {
-        const int e = e0 + le;
-        int k, x, b;
-        entry_block<NX>(m, le, k, x, b);
-        const F* bv = I.bvec + (int64_t)b * NU;
-        double f = 0.0;
-        if (k < T) {
+  // accumulator of sum_j A_hat_j' zeta_j, [(k*NU + u)*NX + x]: in the FP64 form
+  // the LDS of the gain copy Kf (idle from the (du, p) block to the next
+  // K-solve, and exactly this size), else global scratch
+  auto zero_acc = [&](auto* acc) {
+    for (int i = threadIdx.x; i < T * NU * NX; i += blockDim.x) acc[i] = 0.0;
+  };
+  // entry pass: per cone ||eta||^2, ||zeta||^2, zeta.eta, and the adjoint of zeta.
+  // Static schedule over the wave tasks; a long cone is one wave's (its block
+  // vectors staged in the wave's LDS slice, its entries loaded 256 at a time),
+  // packed short cones take one entry per lane with per-cone sums formed by a
+  // segmented suffix sum over the lanes (fixed order).
+  auto entry_pass = [&](auto* acc) {
+    const int lane = lane_id();
+    F* bl = S.bl + wave_id() * (T + 1) * NU;
+    // eta and zeta of entry e of a cone, block k, component x, block vector bv
+    auto eta_zeta = [&](int64_t e, int k, int x, const F* bv, double& eta, double& z) {
+      double f = 0.0;
+      if (k < T) {
 #pragma unroll
-          for (int u = 0; u < NU; ++u) f += (double)bv[u] * I.K[(k * NU + u) * NX + x];
-        }
-        const double eta = r * f + (double)I.bhat[e];
-        double z;
-        if (METHOD == NRTO_DR) {
-          z = sig * ((double)I.st[e] - eta);
-        } else {
-          double lv = (double)I.st[e];
-          if (pending) lv += eta - (double)I.nuv[e];
-          z = -o.rho * lv;
-        }
-        n2 += eta * eta;
-        z2 += z * z;
-        ze += z * eta;
-        if (k < T) {
+        for (int u = 0; u < NU; ++u) f += (double)bv[u] * I.K[(k * NU + u) * NX + x];
+      }
+      eta = r * f + (double)I.bhat[e];
+      if (METHOD == NRTO_DR) {
+        z = sig * ((double)I.st[e] - eta);
+      } else {
+        double lv = (double)I.st[e];
+        if (pending) lv += eta - (double)I.nuv[e];
+        z = -o.rho * lv;
+      }
+    };
+    auto adjoint = [&](int k, int x, const F* bv, double z) {
+      if (k >= T) return;
 #pragma unroll
-          for (int u = 0; u < NU; ++u) {
-            const double cz = r * (double)bv[u] * z;
-            if (cz != 0.0) unsafeAtomicAdd(&I.kscr[(k * NU + u) * NX + x], cz);
+      for (int u = 0; u < NU; ++u) {
+        const double cz = r * (double)bv[u] * z;
+        if (cz != 0.0) atomicAdd(&acc[(k * NU + u) * NX + x], cz);
+      }
+    };
+    for (int t = uni((int)wave_id()); t < I.ntask; t += W) {
+      const WaveTask tk = I.tasks[t];
+      if (tk.ncone == 1 && tk.len > NRTO_WAVE) {
+        const int c = tk.cone, len = tk.len, k0 = tk.k0;
+        const G<F>* bvp = I.bvec + (int64_t)tk.boff * NU;
+        const int nbv = ((len - 1) / NX) * NU;
+        BlockStage<F> bs;
+        bs.load(bvp, nbv, 0);
+        bs.store(bl, nbv, 0);
+        bs.rest(bvp, nbv, bl);
+        wave_sync();
+        double n2 = 0.0, z2 = 0.0, ze = 0.0;
+        constexpr int E = 4;
+        for (int base = 0; base < len; base += E * NRTO_WAVE) {
+#pragma unroll
+          for (int i = 0; i < E; ++i) {
+            const int le = base + lane + i * NRTO_WAVE;
+            if (le >= 1 && le < len) {
+              const int q = le - 1, blk = q / NX, x = q - blk * NX, k = k0 + blk;
+              double eta, z;
+              eta_zeta(tk.ebeg + le, k, x, bl + blk * NU, eta, z);
+              n2 += eta * eta;
+              z2 += z * z;
+              ze += z * eta;
+              adjoint(k, x, bl + blk * NU, z);
+            }
           }
         }
-      }
-      n2 = wave_sum(n2);
-      z2 = wave_sum(z2);
-      ze = wave_sum(ze);
-      if (lane_id() == 0) {
-        I.C(CA_N, c) = sqrt(n2);
-        I.C(CA_ZZ, c) = z2;
-        I.C(CA_ZE, c) = ze;
+        n2 = wave_sum(n2);
+        z2 = wave_sum(z2);
+        ze = wave_sum(ze);
+        if (lane == 0) {
+          I.C(CA_N, c) = sqrt(n2);
+          I.C(CA_ZZ, c) = z2;
+          I.C(CA_ZE, c) = ze;
+        }
+        wave_sync();   // the slice is reused by the wave's next cone
+      } else {
+        const uint64_t mask = I.tmask[t];
+        const int l = lane;
+        const uint64_t pre = mask & ((l == 63) ? ~0ull : ((2ull << l) - 1ull));
+        const uint64_t above = mask & ~((l == 63) ? ~0ull : ((2ull << l) - 1ull));
+        const int cl = __popcll(pre) - 1;
+        const int cs = 63 - __clzll(pre);
+        const int ce = above ? __ffsll((unsigned long long)above) - 1 : tk.len;   // end of this lane's cone
+        const int le = l - cs;
+        const int c = tk.cone + cl;
+        double n2 = 0.0, z2 = 0.0, ze = 0.0;
+        if (l < tk.len && le >= 1) {
+          const int32_t* m = I.cm + c * CM_N;
+          int k, x, b;
+          entry_block<NX>(m, le, k, x, b);
+          const F* bv = I.bvec + (int64_t)b * NU;
+          double eta, z;
+          eta_zeta(tk.ebeg + l, k, x, bv, eta, z);
+          n2 = eta * eta;
+          z2 = z * z;
+          ze = z * eta;
+          adjoint(k, x, bv, z);
+        }
+        // segmented suffix sums: lane l ends with the sum over [l, ce)
+#pragma unroll
+        for (int off = 1; off < NRTO_WAVE; off <<= 1) {
+          const double a = __shfl_down(n2, off, NRTO_WAVE);
+          const double b = __shfl_down(z2, off, NRTO_WAVE);
+          const double d = __shfl_down(ze, off, NRTO_WAVE);
+          if (l + off < ce) {
+            n2 += a;
+            z2 += b;
+            ze += d;
+          }
+        }
+        if (l < tk.len && le == 0) {
+          I.C(CA_N, c) = sqrt(n2);
+          I.C(CA_ZZ, c) = z2;
+          I.C(CA_ZE, c) = ze;
+        }
       }
     }
+  };
+  if constexpr (sizeof(F) == 8) {
+    L<double>* acc = (L<double>*)S.Kf;
+    zero_acc(acc);
+    __syncthreads();
+    entry_pass(acc);
+  } else {
+    zero_acc(I.kscr);
+    __syncthreads();
+    entry_pass(I.kscr);
   }
   __syncthreads();
   // per-cone terms
@@ -2129,7 +2205,9 @@ __device__ double kkt_residual(const Inst<NX, NU, F>& I, Smem<F>& S, const Solve
 #pragma unroll
     for (int w = 0; w < NU; ++w) qk += I.RK2[u * NU + w] * I.K[(k * NU + w) * NX + x];
     qk *= 2.0;
-    const double az = atomic_load_agent(&I.kscr[i]);
+    double az;
+    if constexpr (sizeof(F) == 8) az = ((const L<double>*)S.Kf)[i];
+    else az = atomic_load_agent(&I.kscr[i]);
     t2[0] = fmax(t2[0], fabs(qk - az));
     t2[1] = fmax(t2[1], fabs(qk));
     t2[2] = fmax(t2[2], fabs(az));
