@@ -37,6 +37,7 @@ struct HostInst {
   std::vector<int32_t> cmeta;
   std::vector<WaveTask> tasks;
   std::vector<uint64_t> tmask;
+  std::vector<LaneBlock> lblock;   // 64 per packed task
   std::vector<int32_t> tl;
   std::vector<double> prm;
   std::vector<double> uinit;
@@ -50,7 +51,7 @@ struct nrto_ctx_s {
   DevPtrs g{};
   std::vector<void*> allocs;
   int64_t ncones = 0, nent = 0, nbv = 0, nA = 0, nB = 0, nX = 0, nU = 0, nK = 0, nW = 0, nP = 0, nTL = 0,
-          nG = 0, ntask = 0;
+          nG = 0, ntask = 0, nlb = 0;
   int32_t* order = nullptr;
   std::vector<int32_t> horder;
   int group_nx[3] = {3, 12, 14};
@@ -223,6 +224,21 @@ static nrto_status build_instance(nrto_ctx c, const nrto_problem& p, HostInst& h
   h.tmask.assign(longt.size(), 0ull);
   h.tasks.insert(h.tasks.end(), shortt.begin(), shortt.end());
   h.tmask.insert(h.tmask.end(), shortm.begin(), shortm.end());
+  // lane table of the packed tasks: the block time and block vector of each lane's entry
+  h.lblock.assign(shortt.size() * 64, LaneBlock{-1, -1});
+  for (size_t s = 0; s < shortt.size(); ++s) {
+    const WaveTask& tk = shortt[s];
+    int c = tk.cone;
+    for (int l = 0; l < tk.len; ++l) {
+      const int e = tk.ebeg + l;
+      while (c + 1 < tk.cone + tk.ncone && cm[(c + 1) * CM_N + CM_EOFF] <= e) ++c;
+      const int le = e - cm[c * CM_N + CM_EOFF];
+      if (le == 0) continue;
+      const int blk = (le - 1) / nx;
+      const int k = cm[c * CM_N + CM_K0] + blk;
+      if (k < T) h.lblock[s * 64 + l] = LaneBlock{k, cm[c * CM_N + CM_BOFF] + blk};
+    }
+  }
   h.cmeta = cm;
   h.tl = tls;
   h.tl.insert(h.tl.end(), tlc.begin(), tlc.end());
@@ -268,6 +284,7 @@ static nrto_status build_instance(nrto_ctx c, const nrto_problem& p, HostInst& h
   d.nent = ent;
   d.nblk = blk;
   d.ntask = (int)h.tasks.size();
+  d.nlong = (int)longt.size();
   d.n_obs = p.n_obs;
   d.radius = p.radius;
   d.dt = p.dt;
@@ -396,6 +413,7 @@ extern "C" nrto_status nrto_setup(const nrto_problem* probs, int32_t n, const nr
     d.ent0 = c->nent; c->nent += d.nent;
     d.bv0 = c->nbv; c->nbv += (int64_t)d.nblk * d.nu;
     d.task0 = c->ntask; c->ntask += d.ntask;
+    d.lb0 = c->nlb; c->nlb += (int64_t)(d.ntask - d.nlong);
     d.oA = c->nA; c->nA += (int64_t)d.T * d.nx * d.nx;
     d.oB = c->nB; c->nB += (int64_t)d.T * d.nx * d.nu;
     d.oX = c->nX; c->nX += (int64_t)(d.T + 1) * d.nx;
@@ -443,6 +461,7 @@ extern "C" nrto_status nrto_setup(const nrto_problem* probs, int32_t n, const nr
   ALLOC(g.gch, c->nG);
   ALLOC(g.tasks, c->ntask);
   ALLOC(g.tmask, c->ntask);
+  ALLOC(g.lblock, c->nlb * 64);
   ALLOC(g.mu, n);
   ALLOC(g.iscr, (int64_t)n * ISCR_N);
   ALLOC(g.flags, (int64_t)n * 4);
@@ -457,6 +476,7 @@ extern "C" nrto_status nrto_setup(const nrto_problem* probs, int32_t n, const nr
   std::vector<int32_t> cm;
   std::vector<WaveTask> tk;
   std::vector<uint64_t> tm;
+  std::vector<LaneBlock> lb;
   std::vector<int32_t> tl;
   std::vector<double> prm, u;
   for (int i = 0; i < n; ++i) {
@@ -465,6 +485,7 @@ extern "C" nrto_status nrto_setup(const nrto_problem* probs, int32_t n, const nr
     cm.insert(cm.end(), h.cmeta.begin(), h.cmeta.end());
     tk.insert(tk.end(), h.tasks.begin(), h.tasks.end());
     tm.insert(tm.end(), h.tmask.begin(), h.tmask.end());
+    lb.insert(lb.end(), h.lblock.begin(), h.lblock.end());
     tl.insert(tl.end(), h.tl.begin(), h.tl.end());
     prm.insert(prm.end(), h.prm.begin(), h.prm.end());
     u.insert(u.end(), h.uinit.begin(), h.uinit.end());
@@ -488,6 +509,7 @@ extern "C" nrto_status nrto_setup(const nrto_problem* probs, int32_t n, const nr
   HIPCHK(c, H2D(g.cmeta, cm.data(), sizeof(int32_t) * cm.size()));
   HIPCHK(c, H2D(g.tasks, tk.data(), sizeof(WaveTask) * tk.size()));
   HIPCHK(c, H2D(g.tmask, tm.data(), sizeof(uint64_t) * tm.size()));
+  if (!lb.empty()) HIPCHK(c, H2D(g.lblock, lb.data(), sizeof(LaneBlock) * lb.size()));
   HIPCHK(c, H2D(g.tl, tl.data(), sizeof(int32_t) * tl.size()));
   HIPCHK(c, H2D(g.prm, prm.data(), sizeof(double) * prm.size()));
   HIPCHK(c, H2D(g.uhat, u.data(), sizeof(double) * u.size()));

@@ -23,11 +23,13 @@ struct InstDev {
   int32_t dyn, nx, nu, T;
   int32_t ng, nstate, nent, nblk;
   int32_t ntask, n_obs;
-  int32_t pad0, pad1;
+  int32_t nlong;   // wave tasks of one long cone, listed first; the packed tasks follow
+  int32_t pad1;
   int64_t cone0;   // first cone (global cone index)
   int64_t ent0;    // first cone entry
   int64_t bv0;     // first element of the block vectors (nu per block)
   int64_t task0;   // first wave task
+  int64_t lb0;     // first row of the packed tasks' lane table (64 LaneBlocks a row)
   int64_t oA;      // A: T*nx*nx
   int64_t oB;      // B: T*nx*nu
   int64_t oX;      // xhat: (T+1)*nx  (also dx)
@@ -101,6 +103,14 @@ struct WaveTask {
   int32_t pad0, pad1;
 };
 
+// Block of the entry a lane of a packed wave task holds: block time k and block
+// vector index b (local to the instance); k = -1 for a cone's t slot, a block
+// without gain (k = T) and the lanes past the task.  Row r of the table serves
+// packed task nlong + r of the instance.
+struct LaneBlock {
+  int32_t k, b;
+};
+
 enum { ISCR_PSI = 0, ISCR_KKT, ISCR_RP, ISCR_RD, ISCR_MUHINT, ISCR_N = 8 };
 
 struct SolveOpts {
@@ -140,6 +150,7 @@ struct DevPtrs {
   double* gch;
   WaveTask* tasks;
   uint64_t* tmask;
+  LaneBlock* lblock;   // packed tasks' lane table
   double* mu;          // per instance trust-region multiplier
   double* iscr;        // per instance scratch, ISCR_N doubles
   int32_t* flags;      // per instance: [0] lambda_nu update pending

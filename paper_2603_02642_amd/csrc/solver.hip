@@ -242,6 +242,8 @@ struct Inst {
   const G<int32_t>* tlc;  // control cones by step: [tlc[k], tlc[k+1])
   const G<WaveTask>* tasks;
   const G<uint64_t>* tmask;
+  const G<LaneBlock>* lblock;   // lane table of the packed tasks (tasks nlong, nlong + 1, ...)
+  int nlong;
   G<double>* mu;
   G<double>* iscr;
   G<int32_t>* flags;
@@ -343,6 +345,8 @@ __device__ __forceinline__ Inst<NX, NU, F> uniform_inst(const Inst<NX, NU, F>& I
   U.tlc = uni(I.tlc);
   U.tasks = uni(I.tasks);
   U.tmask = uni(I.tmask);
+  U.lblock = uni(I.lblock);
+  U.nlong = uni(I.nlong);
   U.mu = uni(I.mu);
   U.iscr = uni(I.iscr);
   U.flags = uni(I.flags);
@@ -388,6 +392,8 @@ __device__ Inst<NX, NU, F> make_inst(const DevPtrs& g, int ii) {
   I.tlc = I.tls + (d.T + 2);
   I.tasks = (const G<WaveTask>*)(g.tasks + d.task0);
   I.tmask = (const G<uint64_t>*)(g.tmask + d.task0);
+  I.lblock = (const G<LaneBlock>*)(g.lblock + d.lb0 * 64);
+  I.nlong = d.nlong;
   I.mu = (G<double>*)(g.mu + ii);
   I.iscr = (G<double>*)(g.iscr + (int64_t)ii * ISCR_N);
   I.flags = (G<int32_t>*)(g.flags + (int64_t)ii * 4);
@@ -825,6 +831,7 @@ template <typename F>
 struct DrArgs {
   const WaveTask* tasks;
   const uint64_t* tmask;
+  const LaneBlock* lblock;
   const int32_t* cm;
   double* ca;          // per-cone columns, column stride cstride
   int64_t cstride;
@@ -837,7 +844,7 @@ struct DrArgs {
   double* wscr;
   int* ctr;
   int64_t lds_ctr_off;   // byte offset of ctr in the dynamic LDS
-  int T, ntask;
+  int T, ntask, nlong;
   double r, al, sigma_chi, rho, sig;
 };
 
@@ -866,7 +873,7 @@ __device__ __noinline__ Acc5 dr_pass_impl(DrArgs<F> g) {
   }
   const G<WaveTask>* tasks = (const G<WaveTask>*)g.tasks;
   const G<uint64_t>* tmask = (const G<uint64_t>*)g.tmask;
-  const G<int32_t>* cmeta = (const G<int32_t>*)g.cm;
+  const G<LaneBlock>* lblock = (const G<LaneBlock>*)g.lblock;
   G<double>* ca = (G<double>*)g.ca;
   G<F>* gst = (G<F>*)g.st;
   const G<F>* gbhat = (const G<F>*)g.bhat;
@@ -888,7 +895,9 @@ __device__ __noinline__ Acc5 dr_pass_impl(DrArgs<F> g) {
   // a long cone's first block and block-vector offset come with the
   // descriptor, and its multiplier data are loaded with its entries.
   const int W = (int)(blockDim.x / NRTO_WAVE);
-  auto load_task = [&](int t, WaveTask& k, uint64_t& mask) {
+  // (a packed task's lane-table row follows from its index: the packed tasks
+  // come after the g.nlong long ones, so its load is issued with the descriptor)
+  auto load_task = [&](int t, WaveTask& k, uint64_t& mask, LaneBlock& lb) {
     const G<WaveTask>* p = tasks + t;
     k.cone = p->cone;
     k.ncone = p->ncone;
@@ -897,15 +906,22 @@ __device__ __noinline__ Acc5 dr_pass_impl(DrArgs<F> g) {
     k.k0 = p->k0;
     k.boff = p->boff;
     mask = tmask[t];
+    if (t >= g.nlong) {
+      const G<LaneBlock>* q = lblock + (int64_t)(t - g.nlong) * NRTO_WAVE + lane;
+      lb.k = q->k;
+      lb.b = q->b;
+    }
   };
   int t = uni((int)wave_id());
   WaveTask tk = {0, 0, 0, 0, 0, 0, 0, 0};
   uint64_t tkmask = 0;
-  if (t < g.ntask) load_task(t, tk, tkmask);
+  LaneBlock tklb = {-1, -1};
+  if (t < g.ntask) load_task(t, tk, tkmask, tklb);
   for (; t < g.ntask; t += W) {
     WaveTask tkn = tk;
     uint64_t tknmask = 0;
-    if (t + W < g.ntask) load_task(t + W, tkn, tknmask);
+    LaneBlock tknlb = {-1, -1};
+    if (t + W < g.ntask) load_task(t + W, tkn, tknmask, tknlb);
     if (tk.ncone == 1 && tk.len > NRTO_WAVE) {
       const int c = tk.cone;
       const ConeDual cd = {C(CA_PTT, c), C(CA_P, c), C(CA_LAM, c)};
@@ -926,8 +942,8 @@ __device__ __noinline__ Acc5 dr_pass_impl(DrArgs<F> g) {
         dr_long_cone_2pass<NX, NU, F, DR_STAGE>(tk, st, bh, gbvec, g.Kf, g.Racc, bl, T, r, al, cd, g.sigma_chi,
                                                 rho, sig, den, cpt, cptt, acc);
     } else {
-      // packed short cones: one entry per lane; each lane reads its cone's
-      // metadata and its block vector once
+      // packed short cones: one entry per lane; its block time and block vector
+      // come from the lane table, its cone (for the t slot) from the mask
       const uint64_t mask = tkmask;
       const int l = lane;
       const bool valid = l < tk.len;
@@ -953,15 +969,13 @@ __device__ __noinline__ Acc5 dr_pass_impl(DrArgs<F> g) {
           s = (F)ptc;
           ws[64 + cl] = (double)((F)2 * s - stv);
         } else {
-          const G<int32_t>* m = cmeta + c * CM_N;
-          const int q = le - 1, blk = q / NX;
-          x = q - blk * NX;
-          k = m[CM_K0] + blk;
+          x = (le - 1) % NX;
+          k = tklb.k;
           bh = gbhat[e];
           F f = (F)0;
-          if (k < T) {
+          if (k >= 0) {
             has_gain = true;
-            const G<F>* bv = gbvec + (int64_t)(m[CM_BOFF] + blk) * NU;
+            const G<F>* bv = gbvec + (int64_t)tklb.b * NU;
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
               bvr[u] = bv[u];
@@ -1006,6 +1020,7 @@ __device__ __noinline__ Acc5 dr_pass_impl(DrArgs<F> g) {
     }
     tk = tkn;
     tkmask = tknmask;
+    tklb = tknlb;
   }
 #pragma unroll
   for (int i = 0; i < 5; ++i) out.v[i] = acc[i];
@@ -1018,6 +1033,7 @@ __device__ __forceinline__ void dr_pass(const Inst<NX, NU, F>& I, Smem<F>& S, co
   DrArgs<F> g;
   g.tasks = I.tasks;
   g.tmask = I.tmask;
+  g.lblock = I.lblock;
   g.cm = I.cm;
   g.ca = I.ca;
   g.cstride = I.cstride;
@@ -1032,6 +1048,7 @@ __device__ __forceinline__ void dr_pass(const Inst<NX, NU, F>& I, Smem<F>& S, co
   g.lds_ctr_off = (int64_t)((const char*)S.ctr - (const char*)nrto_dyn_smem);
   g.T = I.T;
   g.ntask = I.ntask;
+  g.nlong = I.nlong;
   g.r = I.r;
   g.al = o.alpha;
   g.sigma_chi = o.sigma_chi;
