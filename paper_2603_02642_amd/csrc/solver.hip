@@ -575,14 +575,16 @@ __device__ __forceinline__ void soc_case(double t, double a, double& that, doubl
 // (independent, so they are in flight together with the block vectors).  It
 // then forms eta(K) from the block vectors and K_k in LDS, reduces the
 // reflected norm, and projects / relaxes / stores its entries.  Up to 64*E
-// entries a lane keeps s~, b_hat and eta of its E entries in registers (one
-// sweep over the cone's data); longer cones take two sweeps (the second reloads
-// s~ and b_hat).  The cone's first block, first block vector and multiplier
+// entries (E = 2, 4, 8 or 12, by the cone's length; see dr_stage) a lane keeps s~,
+// b_hat and eta of its E entries in registers (one sweep over the cone's data);
+// longer cones take two sweeps (the second reloads s~ and b_hat).  The cone's first block, first block vector and multiplier
 // data come with the task.
-#ifndef NRTO_DR_STAGE
-#define NRTO_DR_STAGE 8
-#endif
-constexpr int DR_STAGE = NRTO_DR_STAGE;   // chunks of 64 entries a lane holds in one sweep
+// Chunks of 64 entries a lane holds in one sweep, at most: 12 where the DR pass
+// then still compiles without register spills (n_x = 12, n_u = 4), else 8.
+template <int NX, int NU>
+constexpr int dr_stage() {
+  return (NX == 12 && NU == 4) ? 12 : 8;
+}
 
 // The cone's multiplier data (cd: p~~, p, lambda of the cone, loaded with the
 // cone's entries) enter the t slot: p~ = (sigma_chi p~~ + rho p + lambda +
@@ -895,6 +897,7 @@ __device__ __noinline__ Acc5 dr_pass_impl(DrArgs<F> g) {
   // a long cone's first block and block-vector offset come with the
   // descriptor, and its multiplier data are loaded with its entries.
   const int W = (int)(blockDim.x / NRTO_WAVE);
+  constexpr int DRS = dr_stage<NX, NU>();
   // (a packed task's lane-table row follows from its index: the packed tasks
   // come after the g.nlong long ones, so its load is issued with the descriptor)
   auto load_task = [&](int t, WaveTask& k, uint64_t& mask, LaneBlock& lb) {
@@ -935,12 +938,15 @@ __device__ __noinline__ Acc5 dr_pass_impl(DrArgs<F> g) {
       else if (tk.len <= 4 * NRTO_WAVE)
         dr_long_cone<NX, NU, F, 4>(tk, st, bh, gbvec, g.Kf, g.Racc, bl, T, r, al, cd, g.sigma_chi, rho, sig, den,
                                    cpt, cptt, acc);
-      else if (tk.len <= DR_STAGE * NRTO_WAVE)
-        dr_long_cone<NX, NU, F, DR_STAGE>(tk, st, bh, gbvec, g.Kf, g.Racc, bl, T, r, al, cd, g.sigma_chi, rho, sig,
-                                          den, cpt, cptt, acc);
+      else if (tk.len <= 8 * NRTO_WAVE)
+        dr_long_cone<NX, NU, F, 8>(tk, st, bh, gbvec, g.Kf, g.Racc, bl, T, r, al, cd, g.sigma_chi, rho, sig, den,
+                                   cpt, cptt, acc);
+      else if (DRS > 8 && tk.len <= DRS * NRTO_WAVE)
+        dr_long_cone<NX, NU, F, DRS>(tk, st, bh, gbvec, g.Kf, g.Racc, bl, T, r, al, cd, g.sigma_chi, rho, sig, den,
+                                     cpt, cptt, acc);
       else
-        dr_long_cone_2pass<NX, NU, F, DR_STAGE>(tk, st, bh, gbvec, g.Kf, g.Racc, bl, T, r, al, cd, g.sigma_chi,
-                                                rho, sig, den, cpt, cptt, acc);
+        dr_long_cone_2pass<NX, NU, F, DRS>(tk, st, bh, gbvec, g.Kf, g.Racc, bl, T, r, al, cd, g.sigma_chi, rho, sig,
+                                           den, cpt, cptt, acc);
     } else {
       // packed short cones: one entry per lane; its block time and block vector
       // come from the lane table, its cone (for the t slot) from the mask
