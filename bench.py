@@ -199,7 +199,7 @@ def table_sweep(args, nrto, torch, stream):
         for o in synth.TABLE1_SWEEPS["obs"]:
             points.append((model, "obs", T0, tau0, o))
     pol = dict(TUNED, rho=args.rho, sigma_s=args.sigma_s, sigma_thr=args.sigma_thr, sigma_every=args.sigma_every,
-               eps_dr_abs=args.eps_dr, eps_dr_rel=args.eps_dr)
+               eps_dr_abs=args.eps_dr, eps_dr_rel=args.eps_dr, admm_chunk=args.admm_chunk)
     opt = nrto.default_options(method=nrto.NRTO_DR, precision=nrto.NRTO_FP64, max_admm=args.max_admm,
                                max_inner=args.max_inner, check_every=args.check_every, eps_kkt=1e-4,
                                r_trust=2.0, **pol)
@@ -257,6 +257,8 @@ def main():
     ap.add_argument("--sigma-every", type=int, default=10)
     ap.add_argument("--eps-dr", type=float, default=1e-4,
                     help="inner DR stopping tolerance, absolute and relative")
+    ap.add_argument("--admm-chunk", type=int, default=0,
+                    help="run each solve as launches of at most this many ADMM iterations (0: one launch)")
     ap.add_argument("--cpu-budget", type=float, default=20.0,
                     help="seconds of oracle time for the single-instance workload's CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -293,9 +295,10 @@ def main():
         return
     probs = _problems(args.workload, args.instances or None)
     pol = dict(TUNED, rho=args.rho, sigma_s=args.sigma_s, sigma_thr=args.sigma_thr, sigma_every=args.sigma_every,
-               eps_dr_abs=args.eps_dr, eps_dr_rel=args.eps_dr)
+               eps_dr_abs=args.eps_dr, eps_dr_rel=args.eps_dr, admm_chunk=args.admm_chunk)
     pol_rec = {k: pol[k] for k in ("rho", "sigma_s", "sigma_thr", "sigma_every")}
     pol_rec["eps_dr"] = args.eps_dr
+    pol_rec["admm_chunk"] = args.admm_chunk
     pol_rec["check_every"] = args.check_every
     opt = nrto.default_options(method=nrto.NRTO_DR, precision=nrto.NRTO_FP64, max_admm=args.max_admm,
                                max_inner=args.max_inner, check_every=args.check_every, eps_kkt=1e-4,

@@ -128,7 +128,16 @@ typedef struct {
                                 fallen below 0.99 times its smallest earlier value for this many
                                 ADMM iterations while r_p / (1 + ||p~||) > 1e-3 (the linearised
                                 problem may be infeasible, e.g. inside a small trust region) */
-  int32_t pad0;
+  int32_t admm_chunk;        /* 0 = a solve is one launch; else a solve is run as launches of at
+                                most admm_chunk ADMM iterations each (max_admm in total).  An
+                                instance continues from its device state (method state, sigma_s,
+                                rho, trust-region multiplier) in the next launch while it has not
+                                stopped; stopped instances return at once, so that the slowest
+                                solves of a batch are not started late behind the others.  The
+                                report sums the counts and times of an instance's launches; the
+                                stagnation window (infeas_window) restarts with each launch.
+                                Same iterates as one launch up to the order of floating-point
+                                sums. */
 } nrto_options;
 
 /* Per-instance result of a solve. */

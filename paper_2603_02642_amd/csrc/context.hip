@@ -318,7 +318,7 @@ static void fill_opts(const nrto_ctx c, SolveOpts& o, int warm) {
   o.sigma_min = c->opt.sigma_min;
   o.sigma_max = c->opt.sigma_max;
   o.infeas_window = c->opt.infeas_window;
-  o.pad0 = 0;
+  o.cont = 0;
 }
 
 static nrto_status check_options(nrto_ctx c, const nrto_options* o) {
@@ -333,6 +333,7 @@ static nrto_status check_options(nrto_ctx c, const nrto_options* o) {
     return ctx_err(c, NRTO_ERR_ARG, "block_threads must be 0 or a multiple of 64 in [64, 1024]");
   if (o->cold_init != 0 && o->cold_init != 1) return ctx_err(c, NRTO_ERR_ARG, "cold_init must be 0 or 1");
   if (o->infeas_window < 0) return ctx_err(c, NRTO_ERR_ARG, "infeas_window must be >= 0");
+  if (o->admm_chunk < 0) return ctx_err(c, NRTO_ERR_ARG, "admm_chunk must be >= 0");
   if (o->rho_adapt != 0 && o->rho_adapt != 1) return ctx_err(c, NRTO_ERR_ARG, "rho_adapt must be 0 or 1");
   if (o->rho_adapt &&
       !(o->rho_mu > 1 && o->rho_tau > 1 && o->rho_min > 0 && o->rho_min <= o->rho && o->rho <= o->rho_max))
@@ -638,16 +639,26 @@ static nrto_status launch_solve(nrto_ctx c, int warm, const DevPtrs& g) {
   int groups[3], ng = 0;
   for (int gi = 0; gi < 3; ++gi)
     if (c->group_off[gi + 1] > c->group_off[gi]) groups[ng++] = gi;
-  if (ng > 1) HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
-  for (int j = 0; j < ng; ++j) {
-    const int gi = groups[j];
-    hipStream_t s = (j == 0) ? c->stream : c->aux[j - 1];
-    if (j > 0) HIPCHK(c, hipStreamWaitEvent(s, c->ev_fork, 0));
-    const int cnt = c->group_off[gi + 1] - c->group_off[gi];
-    HIPCHK(c, launch_solver(g, o, c->group_nx[gi], c->order + c->group_off[gi], cnt, c->threads, c->smem, s));
-    if (j > 0) {
-      HIPCHK(c, hipEventRecord(c->ev_join[j - 1], s));
-      HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join[j - 1], 0));
+  // chunked solve: launches of at most admm_chunk ADMM iterations; the later
+  // ones continue the instances that have not stopped (a fixed number of
+  // launches, so a captured step replays them all)
+  const int total = c->opt.max_admm;
+  const int chunk = (c->opt.admm_chunk > 0 && c->opt.admm_chunk < total) ? c->opt.admm_chunk : total;
+  for (int done = 0; done < total; done += chunk) {
+    o.max_admm = std::min(chunk, total - done);
+    o.cont = done > 0 ? 1 : 0;
+    o.warm = done > 0 ? 1 : warm;
+    if (ng > 1) HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
+    for (int j = 0; j < ng; ++j) {
+      const int gi = groups[j];
+      hipStream_t s = (j == 0) ? c->stream : c->aux[j - 1];
+      if (j > 0) HIPCHK(c, hipStreamWaitEvent(s, c->ev_fork, 0));
+      const int cnt = c->group_off[gi + 1] - c->group_off[gi];
+      HIPCHK(c, launch_solver(g, o, c->group_nx[gi], c->order + c->group_off[gi], cnt, c->threads, c->smem, s));
+      if (j > 0) {
+        HIPCHK(c, hipEventRecord(c->ev_join[j - 1], s));
+        HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join[j - 1], 0));
+      }
     }
   }
   return NRTO_OK;

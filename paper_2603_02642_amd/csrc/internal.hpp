@@ -119,7 +119,8 @@ struct SolveOpts {
   double rho_mu, rho_tau, rho_min, rho_max;
   int32_t sigma_adapt, sigma_every;
   double sigma_thr, sigma_min, sigma_max;
-  int32_t infeas_window, pad0;
+  int32_t infeas_window;
+  int32_t cont;   // continuation launch of a solve run in chunks of ADMM iterations (admm_chunk)
 };
 
 // Device pointers the kernels use.

@@ -2436,11 +2436,18 @@ __device__ void cold_state(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts
 
 template <int NX, int NU, typename F, int METHOD>
 __device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, L<char>* smem) {
+  // a continuation launch of a chunked solve only runs instances that reached
+  // the previous launch's iteration limit (block-uniform: one report per block)
+  nrto_solve_report prev;
+  if (o.cont) {
+    prev = g.rep[ii];
+    if (prev.status != NRTO_MAXITER) return;
+  }
   Inst<NX, NU, F> I = make_inst<NX, NU, F>(g, ii);
   const int W = blockDim.x / NRTO_WAVE;
   Smem<F> S = carve<F>(smem, I.T, NX, NU, W);
   const int T = I.T;
-  double rho = o.rho;
+  double rho = (o.cont && prev.rho > 0.0) ? prev.rho : o.rho;
   // phase timers (device wall clock ticks, read by thread 0 after block barriers)
   const long long t_start = wall_clock64();
   long long t_dr = 0, t_qp = 0, t_kkt = 0, t_mark = 0;
@@ -2469,11 +2476,18 @@ __device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, L<c
     __syncthreads();
   }
 
-  int admm = 0, inner = 0, qpn = 0, status = NRTO_MAXITER, sig_updates = 0, nan_flag = 0;
+  // a continuation launch counts on from the previous launch of the solve, so
+  // that the schedules that depend on the counts (sigma_s balancing every
+  // sigma_every DR iterations, the KKT check every check_every ADMM iterations)
+  // are those of one launch
+  const int l0 = o.cont ? prev.admm_iters : 0;
+  int admm = l0, inner = o.cont ? prev.inner_iters : 0, qpn = o.cont ? prev.qp_newton : 0;
+  int status = NRTO_MAXITER, sig_updates = o.cont ? prev.sigma_updates : 0, nan_flag = 0;
   double rp_best = 1e300;   // smallest consensus residual so far and its ADMM iteration
-  int l_best = 0;
+  int l_best = l0;
   double kkt = 1e300, rp = 0.0, rd = 0.0;
-  for (int l = 1; l <= o.max_admm; ++l) {
+  const int l_end = l0 + o.max_admm;
+  for (int l = l0 + 1; l <= l_end; ++l) {
     admm = l;
     t_mark = wall_clock64();
     if (METHOD == NRTO_DR) {
@@ -2580,7 +2594,7 @@ __device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, L<c
       break;
     }
     if (METHOD == NRTO_DR) rd = rho * sqrt(acc2[1]);
-    if (o.eps_kkt > 0.0 && (l % o.check_every == 0 || l == o.max_admm)) {
+    if (o.eps_kkt > 0.0 && (l % o.check_every == 0 || l == l_end)) {
       kkt = kkt_residual<NX, NU, F, METHOD>(I, S, o, sig, pending, W);
       t_kkt += wall_clock64() - t_mark;
       if (kkt <= o.eps_kkt) {
@@ -2633,6 +2647,13 @@ __device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, L<c
     rep.t_qp_us = (double)t_qp;
     rep.t_kkt_us = (double)t_kkt;
     rep.t_total_us = (double)(wall_clock64() - t_start);
+    if (o.cont) {   // times of the whole solve (the counts went on from the previous launch)
+      rep.nan_flag = (rep.nan_flag || prev.nan_flag) ? 1 : 0;
+      rep.t_dr_us += prev.t_dr_us;
+      rep.t_qp_us += prev.t_qp_us;
+      rep.t_kkt_us += prev.t_kkt_us;
+      rep.t_total_us += prev.t_total_us;
+    }
     g.rep[ii] = rep;
   }
 }

@@ -41,7 +41,7 @@ class Options(C.Structure):
                 ("rho_adapt", C.c_int32), ("rho_mu", C.c_double), ("rho_tau", C.c_double),
                 ("rho_min", C.c_double), ("rho_max", C.c_double), ("sigma_adapt", C.c_int32),
                 ("sigma_every", C.c_int32), ("sigma_thr", C.c_double), ("sigma_min", C.c_double),
-                ("sigma_max", C.c_double), ("infeas_window", C.c_int32), ("pad0", C.c_int32)]
+                ("sigma_max", C.c_double), ("infeas_window", C.c_int32), ("admm_chunk", C.c_int32)]
 
 
 class SolveReport(C.Structure):

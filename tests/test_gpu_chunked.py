@@ -1,0 +1,74 @@
+"""Chunked solves (nrto_options.admm_chunk): a solve run as launches of at most
+admm_chunk ADMM iterations, each instance continuing from its device state,
+gives the iterates of the same solve in one launch (up to the order of
+floating-point sums), and the same solves to tolerance on a batch of the
+held-out quadrotor SOCPs."""
+import numpy as np
+import pytest
+
+import synth
+from paper_2603_02642_amd import nrto
+
+from helpers import rel_err
+
+pytestmark = pytest.mark.gpu
+
+POLICY = dict(rho=50.0, sigma_s=100.0, cold_init=1, sigma_adapt=1, sigma_thr=2.0, check_every=5, r_trust=2.0)
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _solve(probs, **kw):
+    c = nrto.Context(probs, nrto.default_options(method=0, precision=0, **POLICY, **kw))
+    c.linearize()
+    c.solve()
+    reps = c.reports()
+    sols = [c.solution(i) for i in range(len(probs))]
+    c.close()
+    return reps, sols
+
+
+def test_chunked_iterates_equal_one_launch():
+    torch = _torch()
+    torch.cuda.set_device(0)
+    probs = [synth.config5_instance(i, "heldout") for i in range(32)]
+    fixed = dict(max_admm=12, max_inner=100, eps_kkt=0.0)   # no early exit: 12 ADMM iterations each
+    r1, s1 = _solve(probs, admm_chunk=0, **fixed)
+    r2, s2 = _solve(probs, admm_chunk=5, **fixed)     # launches of 5, 5 and 2 iterations
+    for a, b, x, y in zip(r1, r2, s1, s2):
+        assert a.admm_iters == b.admm_iters == 12
+        assert a.inner_iters == b.inner_iters
+        assert rel_err(y["du"], x["du"]) <= 1e-8
+        assert rel_err(y["K"], x["K"]) <= 1e-8
+
+
+def test_chunked_solves_to_tolerance_match_one_launch():
+    torch = _torch()
+    torch.cuda.set_device(0)
+    probs = [synth.config5_instance(i, "heldout") for i in range(64)]
+    tol = dict(max_admm=200, max_inner=100, eps_kkt=1e-4)
+    r1, s1 = _solve(probs, admm_chunk=0, **tol)
+    r2, s2 = _solve(probs, admm_chunk=20, **tol)
+    conv1 = np.array([r.status == 0 for r in r1])
+    conv2 = np.array([r.status == 0 for r in r2])
+    assert abs(int(conv1.sum()) - int(conv2.sum())) <= 1
+    assert conv1.sum() >= 56
+    for a, b, x, y in zip(r1, r2, s1, s2):
+        if b.status == 0:
+            assert b.kkt <= 1e-4
+        assert b.admm_iters <= 200
+        if a.status == 0 and b.status == 0:
+            assert abs(a.admm_iters - b.admm_iters) <= 2 * POLICY["check_every"]
+            assert rel_err(y["du"], x["du"]) <= 1e-2
+
+
+def test_negative_chunk_is_rejected():
+    torch = _torch()
+    torch.cuda.set_device(0)
+    with pytest.raises(RuntimeError, match="admm_chunk"):
+        nrto.Context([synth.config5_instance(0, "heldout")], nrto.default_options(method=0, admm_chunk=-1))
