@@ -2056,6 +2056,140 @@ __device__ __noinline__ int qp_block(const Inst<NX, NU, F> Iarg, QPScratch<NX, N
 }
 
 // ----------------------------------------------------------------------------
+// KKT check entry pass: per cone ||eta||^2, ||zeta||^2, zeta.eta, and the
+// adjoint sum_j A_hat_j' zeta_j into acc (K read from kk).  Static schedule over
+// the wave tasks; a long cone is one wave's (its block vectors staged in the
+// wave's LDS slice, its entries loaded 256 at a time), packed short cones take
+// one entry per lane with per-cone sums formed by a segmented suffix sum over
+// the lanes (fixed order).  Compiled on its own (like the DR pass), with the
+// instance view by value and made wave-uniform.
+template <int NX, int NU, typename F, int METHOD, typename AccP, typename KP>
+__device__ __noinline__ void kkt_entry_pass(const Inst<NX, NU, F> Iarg, AccP acc, KP kk, L<F>* bl_all, double sig,
+                                            double rho_fa, int pending_i) {
+  const Inst<NX, NU, F> I = uniform_inst(Iarg);
+  const int T = I.T;
+  const double r = I.r;
+  const bool pending = pending_i != 0;
+  const int W = (int)(blockDim.x / NRTO_WAVE);
+  const int lane = lane_id();
+  F* bl = bl_all + wave_id() * (T + 1) * NU;
+  // eta and zeta of entry e of a cone (s~ and b_hat of the entry already
+  // loaded), block k, component x, block vector bv
+  auto eta_zeta = [&](int64_t e, double st_e, double bh_e, int k, int x, const F* bv, double& eta, double& z) {
+    double f = 0.0;
+    if (k < T) {
+#pragma unroll
+      for (int u = 0; u < NU; ++u) f += (double)bv[u] * kk[(k * NU + u) * NX + x];
+    }
+    eta = r * f + bh_e;
+    if (METHOD == NRTO_DR) {
+      z = sig * (st_e - eta);
+    } else {
+      double lv = st_e;
+      if (pending) lv += eta - (double)I.nuv[e];
+      z = -rho_fa * lv;
+    }
+  };
+  auto adjoint = [&](int k, int x, const F* bv, double z) {
+    if (k >= T) return;
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const double cz = r * (double)bv[u] * z;
+      if (cz != 0.0) atomicAdd(&acc[(k * NU + u) * NX + x], cz);
+    }
+  };
+  for (int t = uni((int)wave_id()); t < I.ntask; t += W) {
+    const WaveTask tk = I.tasks[t];
+    if (tk.ncone == 1 && tk.len > NRTO_WAVE) {
+      const int c = tk.cone, len = tk.len, k0 = tk.k0;
+      const G<F>* bvp = I.bvec + (int64_t)tk.boff * NU;
+      const int nbv = ((len - 1) / NX) * NU;
+      BlockStage<F> bs;
+      bs.load(bvp, nbv, 0);
+      bs.store(bl, nbv, 0);
+      bs.rest(bvp, nbv, bl);
+      wave_sync();
+      double n2 = 0.0, z2 = 0.0, ze = 0.0;
+      constexpr int E = 4;
+      for (int base = 0; base < len; base += E * NRTO_WAVE) {
+        // the group's loads first, so that they are in flight together
+        double stv[E], bhv[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          const int le = base + lane + i * NRTO_WAVE;
+          const bool in = le >= 1 && le < len;
+          stv[i] = in ? (double)I.st[tk.ebeg + le] : 0.0;
+          bhv[i] = in ? (double)I.bhat[tk.ebeg + le] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          const int le = base + lane + i * NRTO_WAVE;
+          if (le >= 1 && le < len) {
+            const int q = le - 1, blk = q / NX, x = q - blk * NX, k = k0 + blk;
+            double eta, z;
+            eta_zeta(tk.ebeg + le, stv[i], bhv[i], k, x, bl + blk * NU, eta, z);
+            n2 += eta * eta;
+            z2 += z * z;
+            ze += z * eta;
+            adjoint(k, x, bl + blk * NU, z);
+          }
+        }
+      }
+      n2 = wave_sum(n2);
+      z2 = wave_sum(z2);
+      ze = wave_sum(ze);
+      if (lane == 0) {
+        I.C(CA_N, c) = sqrt(n2);
+        I.C(CA_ZZ, c) = z2;
+        I.C(CA_ZE, c) = ze;
+      }
+      wave_sync();   // the slice is reused by the wave's next cone
+    } else {
+      const uint64_t mask = I.tmask[t];
+      const int l = lane;
+      const uint64_t pre = mask & ((l == 63) ? ~0ull : ((2ull << l) - 1ull));
+      const uint64_t above = mask & ~((l == 63) ? ~0ull : ((2ull << l) - 1ull));
+      const int cl = __popcll(pre) - 1;
+      const int cs = 63 - __clzll(pre);
+      const int ce = above ? __ffsll((unsigned long long)above) - 1 : tk.len;   // end of this lane's cone
+      const int le = l - cs;
+      const int c = tk.cone + cl;
+      double n2 = 0.0, z2 = 0.0, ze = 0.0;
+      if (l < tk.len && le >= 1) {
+        // block time and block vector of the lane's entry from the lane table
+        // (k = -1: a block without gain)
+        const LaneBlock lb = I.lblock[(int64_t)(t - I.nlong) * NRTO_WAVE + l];
+        const int x = (le - 1) % NX;
+        const int k = lb.k >= 0 ? lb.k : T;
+        const F* bv = I.bvec + (int64_t)(lb.k >= 0 ? lb.b : 0) * NU;
+        double eta, z;
+        eta_zeta(tk.ebeg + l, (double)I.st[tk.ebeg + l], (double)I.bhat[tk.ebeg + l], k, x, bv, eta, z);
+        n2 = eta * eta;
+        z2 = z * z;
+        ze = z * eta;
+        adjoint(k, x, bv, z);
+      }
+      // segmented suffix sums: lane l ends with the sum over [l, ce)
+#pragma unroll
+      for (int off = 1; off < NRTO_WAVE; off <<= 1) {
+        const double a = __shfl_down(n2, off, NRTO_WAVE);
+        const double b = __shfl_down(z2, off, NRTO_WAVE);
+        const double d = __shfl_down(ze, off, NRTO_WAVE);
+        if (l + off < ce) {
+          n2 += a;
+          z2 += b;
+          ze += d;
+        }
+      }
+      if (l < tk.len && le == 0) {
+        I.C(CA_N, c) = sqrt(n2);
+        I.C(CA_ZZ, c) = z2;
+        I.C(CA_ZE, c) = ze;
+      }
+    }
+  }
+}
+
 // FP64 KKT residual (see the oracle's definition).  Uses K (double), the
 // multipliers CA_PI, mu, and zeta from the method state.
 template <int NX, int NU, typename F, int METHOD>
@@ -2063,133 +2197,26 @@ __device__ double kkt_residual(const Inst<NX, NU, F>& I, Smem<F>& S, const Solve
                                int W) {
   const int T = I.T;
   const double r = I.r;
-  // accumulator of sum_j A_hat_j' zeta_j, [(k*NU + u)*NX + x]: in the FP64 form
-  // the LDS of the gain copy Kf (idle from the (du, p) block to the next
-  // K-solve, and exactly this size), else global scratch
-  auto zero_acc = [&](auto* acc) {
-    for (int i = threadIdx.x; i < T * NU * NX; i += blockDim.x) acc[i] = 0.0;
-  };
-  // entry pass: per cone ||eta||^2, ||zeta||^2, zeta.eta, and the adjoint of zeta.
-  // Static schedule over the wave tasks; a long cone is one wave's (its block
-  // vectors staged in the wave's LDS slice, its entries loaded 256 at a time),
-  // packed short cones take one entry per lane with per-cone sums formed by a
-  // segmented suffix sum over the lanes (fixed order).
-  auto entry_pass = [&](auto* acc) {
-    const int lane = lane_id();
-    F* bl = S.bl + wave_id() * (T + 1) * NU;
-    // eta and zeta of entry e of a cone, block k, component x, block vector bv
-    auto eta_zeta = [&](int64_t e, int k, int x, const F* bv, double& eta, double& z) {
-      double f = 0.0;
-      if (k < T) {
-#pragma unroll
-        for (int u = 0; u < NU; ++u) f += (double)bv[u] * I.K[(k * NU + u) * NX + x];
-      }
-      eta = r * f + (double)I.bhat[e];
-      if (METHOD == NRTO_DR) {
-        z = sig * ((double)I.st[e] - eta);
-      } else {
-        double lv = (double)I.st[e];
-        if (pending) lv += eta - (double)I.nuv[e];
-        z = -o.rho * lv;
-      }
-    };
-    auto adjoint = [&](int k, int x, const F* bv, double z) {
-      if (k >= T) return;
-#pragma unroll
-      for (int u = 0; u < NU; ++u) {
-        const double cz = r * (double)bv[u] * z;
-        if (cz != 0.0) atomicAdd(&acc[(k * NU + u) * NX + x], cz);
-      }
-    };
-    for (int t = uni((int)wave_id()); t < I.ntask; t += W) {
-      const WaveTask tk = I.tasks[t];
-      if (tk.ncone == 1 && tk.len > NRTO_WAVE) {
-        const int c = tk.cone, len = tk.len, k0 = tk.k0;
-        const G<F>* bvp = I.bvec + (int64_t)tk.boff * NU;
-        const int nbv = ((len - 1) / NX) * NU;
-        BlockStage<F> bs;
-        bs.load(bvp, nbv, 0);
-        bs.store(bl, nbv, 0);
-        bs.rest(bvp, nbv, bl);
-        wave_sync();
-        double n2 = 0.0, z2 = 0.0, ze = 0.0;
-        constexpr int E = 4;
-        for (int base = 0; base < len; base += E * NRTO_WAVE) {
-#pragma unroll
-          for (int i = 0; i < E; ++i) {
-            const int le = base + lane + i * NRTO_WAVE;
-            if (le >= 1 && le < len) {
-              const int q = le - 1, blk = q / NX, x = q - blk * NX, k = k0 + blk;
-              double eta, z;
-              eta_zeta(tk.ebeg + le, k, x, bl + blk * NU, eta, z);
-              n2 += eta * eta;
-              z2 += z * z;
-              ze += z * eta;
-              adjoint(k, x, bl + blk * NU, z);
-            }
-          }
-        }
-        n2 = wave_sum(n2);
-        z2 = wave_sum(z2);
-        ze = wave_sum(ze);
-        if (lane == 0) {
-          I.C(CA_N, c) = sqrt(n2);
-          I.C(CA_ZZ, c) = z2;
-          I.C(CA_ZE, c) = ze;
-        }
-        wave_sync();   // the slice is reused by the wave's next cone
-      } else {
-        const uint64_t mask = I.tmask[t];
-        const int l = lane;
-        const uint64_t pre = mask & ((l == 63) ? ~0ull : ((2ull << l) - 1ull));
-        const uint64_t above = mask & ~((l == 63) ? ~0ull : ((2ull << l) - 1ull));
-        const int cl = __popcll(pre) - 1;
-        const int cs = 63 - __clzll(pre);
-        const int ce = above ? __ffsll((unsigned long long)above) - 1 : tk.len;   // end of this lane's cone
-        const int le = l - cs;
-        const int c = tk.cone + cl;
-        double n2 = 0.0, z2 = 0.0, ze = 0.0;
-        if (l < tk.len && le >= 1) {
-          const int32_t* m = I.cm + c * CM_N;
-          int k, x, b;
-          entry_block<NX>(m, le, k, x, b);
-          const F* bv = I.bvec + (int64_t)b * NU;
-          double eta, z;
-          eta_zeta(tk.ebeg + l, k, x, bv, eta, z);
-          n2 = eta * eta;
-          z2 = z * z;
-          ze = z * eta;
-          adjoint(k, x, bv, z);
-        }
-        // segmented suffix sums: lane l ends with the sum over [l, ce)
-#pragma unroll
-        for (int off = 1; off < NRTO_WAVE; off <<= 1) {
-          const double a = __shfl_down(n2, off, NRTO_WAVE);
-          const double b = __shfl_down(z2, off, NRTO_WAVE);
-          const double d = __shfl_down(ze, off, NRTO_WAVE);
-          if (l + off < ce) {
-            n2 += a;
-            z2 += b;
-            ze += d;
-          }
-        }
-        if (l < tk.len && le == 0) {
-          I.C(CA_N, c) = sqrt(n2);
-          I.C(CA_ZZ, c) = z2;
-          I.C(CA_ZE, c) = ze;
-        }
-      }
-    }
-  };
+  // accumulator of sum_j A_hat_j' zeta_j, [(k*NU + u)*NX + x].  In the FP64
+  // form it takes the LDS of the adjoint accumulator Racc, whose contents (the
+  // next K-solve's input) are saved to global scratch meanwhile and restored at
+  // the end, and K is read from the LDS of the gain copy Kf (idle from the
+  // (du, p) block to the next K-solve); else the accumulator is global scratch
+  // and K is read from global memory.
   if constexpr (sizeof(F) == 8) {
-    L<double>* acc = (L<double>*)S.Kf;
-    zero_acc(acc);
+    L<double>* acc = (L<double>*)S.Racc;
+    L<double>* kl = (L<double>*)S.Kf;
+    for (int i = threadIdx.x; i < T * NU * NX; i += blockDim.x) {
+      I.kscr[i] = acc[i];
+      acc[i] = 0.0;
+      kl[i] = I.K[i];
+    }
     __syncthreads();
-    entry_pass(acc);
+    kkt_entry_pass<NX, NU, F, METHOD>(I, acc, (const L<double>*)kl, S.bl, sig, o.rho, pending ? 1 : 0);
   } else {
-    zero_acc(I.kscr);
+    for (int i = threadIdx.x; i < T * NU * NX; i += blockDim.x) I.kscr[i] = 0.0;
     __syncthreads();
-    entry_pass(I.kscr);
+    kkt_entry_pass<NX, NU, F, METHOD>(I, I.kscr, (const G<double>*)I.K, S.bl, sig, o.rho, pending ? 1 : 0);
   }
   __syncthreads();
   // per-cone terms
@@ -2229,7 +2256,7 @@ __device__ double kkt_residual(const Inst<NX, NU, F>& I, Smem<F>& S, const Solve
     for (int w = 0; w < NU; ++w) qk += I.RK2[u * NU + w] * I.K[(k * NU + w) * NX + x];
     qk *= 2.0;
     double az;
-    if constexpr (sizeof(F) == 8) az = ((const L<double>*)S.Kf)[i];
+    if constexpr (sizeof(F) == 8) az = ((const L<double>*)S.Racc)[i];
     else az = atomic_load_agent(&I.kscr[i]);
     t2[0] = fmax(t2[0], fabs(qk - az));
     t2[1] = fmax(t2[1], fabs(qk));
@@ -2322,6 +2349,11 @@ __device__ double kkt_residual(const Inst<NX, NU, F>& I, Smem<F>& S, const Solve
   res = fmax(res, nm2[2] / (1.0 + nm2[1]));
   res = fmax(res, fabs(fmin(mu, rt - psi)) / (1.0 + fmax(mu, rt)));
   __syncthreads();
+  if constexpr (sizeof(F) == 8) {   // the next K-solve's adjoint back into Racc
+    L<double>* acc = (L<double>*)S.Racc;
+    for (int i = threadIdx.x; i < T * NU * NX; i += blockDim.x) acc[i] = I.kscr[i];
+    __syncthreads();
+  }
   return res;
 }
 
