@@ -1750,23 +1750,47 @@ __device__ __noinline__ void riccati(const Inst<NX, NU, F> Iarg, QPScratch<NX, N
   }
 }
 
+// Cones are taken CB per lane at a time: the loads of a batch (metadata, then
+// gradient rows and states) are issued before its results are stored, so that
+// the batch's dependent load chains overlap.
+constexpr int CB = 4;
+
 // Set CA_ACT from the iterate (du, dx); returns the number of flags that changed.
 template <int NX, int NU, typename F>
 __device__ int set_active(const Inst<NX, NU, F>& I, const double* dx, const double* du) {
   int changed = 0;
-  for (int c = lane_id(); c < I.ng; c += NRTO_WAVE) {
-    const double a = I.C(CA_BETA, c) + cons_lin<NX, NU, F>(I, c, dx, du);
-    const double f = a > 0.0 ? 1.0 : 0.0;
-    if (f != I.C(CA_ACT, c)) ++changed;
-    I.C(CA_ACT, c) = f;
+  for (int c0 = lane_id(); c0 < I.ng; c0 += CB * NRTO_WAVE) {
+    double f[CB], old[CB];
+#pragma unroll
+    for (int i = 0; i < CB; ++i) {
+      const int c = c0 + i * NRTO_WAVE;
+      f[i] = old[i] = 0.0;
+      if (c < I.ng) {
+        const double a = I.C(CA_BETA, c) + cons_lin<NX, NU, F>(I, c, dx, du);
+        f[i] = a > 0.0 ? 1.0 : 0.0;
+        old[i] = I.C(CA_ACT, c);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < CB; ++i) {
+      const int c = c0 + i * NRTO_WAVE;
+      if (c < I.ng) {
+        if (f[i] != old[i]) ++changed;
+        I.C(CA_ACT, c) = f[i];
+      }
+    }
   }
   wave_sync();
   return (int)wave_sum((double)changed);
 }
 
 // Exact line search along (du2 - du, dx2 - dx) for the squared-hinge objective.
+// Each cone's (a, e) (the constraint's value at the iterate and its change along
+// the direction) is kept in the LDS of the Riccati gains (idle until the next
+// sweep) when 2 n_g doubles fit there, else in its per-cone columns; the
+// piecewise-linear derivative is then evaluated from there at every trial step.
 template <int NX, int NU, typename F>
-__device__ double line_search(const Inst<NX, NU, F>& I, double rho, double mu) {
+__device__ double line_search(const Inst<NX, NU, F>& I, const QPScratch<NX, NU>& q, double rho, double mu) {
   const int lane = lane_id();
   const int T = I.T;
   double dHd = 0.0, gd = 0.0;
@@ -1798,18 +1822,47 @@ __device__ double line_search(const Inst<NX, NU, F>& I, double rho, double mu) {
   }
   dHd = wave_sum(dHd);
   gd = wave_sum(gd);
-  for (int c = lane; c < I.ng; c += NRTO_WAVE) {
-    const double a0 = cons_lin<NX, NU, F>(I, c, I.dx, I.du);
-    const double a1 = cons_lin<NX, NU, F>(I, c, I.dx2, I.du2);
-    I.C(CA_LA, c) = I.C(CA_BETA, c) + a0;
-    I.C(CA_LE, c) = a1 - a0;
+  const bool in_lds = 2 * I.ng <= T * NU * NX;
+  L<double>* lae = q.gfb;   // [2c]: a, [2c + 1]: e
+  for (int c0 = lane; c0 < I.ng; c0 += CB * NRTO_WAVE) {
+    double av[CB], ev[CB];
+#pragma unroll
+    for (int i = 0; i < CB; ++i) {
+      const int c = c0 + i * NRTO_WAVE;
+      av[i] = ev[i] = 0.0;
+      if (c < I.ng) {
+        const double a0 = cons_lin<NX, NU, F>(I, c, I.dx, I.du);
+        const double a1 = cons_lin<NX, NU, F>(I, c, I.dx2, I.du2);
+        av[i] = I.C(CA_BETA, c) + a0;
+        ev[i] = a1 - a0;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < CB; ++i) {
+      const int c = c0 + i * NRTO_WAVE;
+      if (c >= I.ng) continue;
+      if (in_lds) {
+        lae[2 * c] = av[i];
+        lae[2 * c + 1] = ev[i];
+      } else {
+        I.C(CA_LA, c) = av[i];
+        I.C(CA_LE, c) = ev[i];
+      }
+    }
   }
   wave_sync();
   if (dHd <= 0.0) return 0.0;
   auto deriv = [&](double s, double& slope) {
     double f = 0.0, sl = 0.0;
     for (int c = lane; c < I.ng; c += NRTO_WAVE) {
-      const double a = I.C(CA_LA, c), e = I.C(CA_LE, c);
+      double a, e;
+      if (in_lds) {
+        a = lae[2 * c];
+        e = lae[2 * c + 1];
+      } else {
+        a = I.C(CA_LA, c);
+        e = I.C(CA_LE, c);
+      }
       const double z = a + s * e;
       if (z > 0.0) {
         f += e * z;
@@ -1872,9 +1925,15 @@ __device__ int ssn(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double rho, d
     ++solves;
     // does the candidate keep the active set?
     int changed = 0;
-    for (int c = lane; c < I.ng; c += NRTO_WAVE) {
-      const double a = I.C(CA_BETA, c) + cons_lin<NX, NU, F>(I, c, I.dx2, I.du2);
-      if ((a > 0.0 ? 1.0 : 0.0) != I.C(CA_ACT, c)) ++changed;
+    for (int c0 = lane; c0 < I.ng; c0 += CB * NRTO_WAVE) {
+#pragma unroll
+      for (int i = 0; i < CB; ++i) {
+        const int c = c0 + i * NRTO_WAVE;
+        if (c < I.ng) {
+          const double a = I.C(CA_BETA, c) + cons_lin<NX, NU, F>(I, c, I.dx2, I.du2);
+          if ((a > 0.0 ? 1.0 : 0.0) != I.C(CA_ACT, c)) ++changed;
+        }
+      }
     }
     changed = (int)wave_sum((double)changed);
     if (changed == 0) {
@@ -1883,7 +1942,7 @@ __device__ int ssn(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double rho, d
       wave_sync();
       break;
     }
-    const double s = line_search<NX, NU, F>(I, rho, mu);
+    const double s = line_search<NX, NU, F>(I, q, rho, mu);
     double step = 0.0;
     for (int i = lane; i < T * NU; i += NRTO_WAVE) {
       const double d = s * (I.du2[i] - I.du[i]);
