@@ -76,7 +76,7 @@ struct Smem {
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
 __host__ __device__ inline size_t qp_scratch_doubles(int nx, int nu) {
-  return 2 * nx * nx + nx + nx * nu + 2 * nu * nu + nu * nx + nu + 2 * nx + 64 +
+  return 2 * nx * nx + nx + nx * nu + nu * nu + nu * nx + nu + 2 * nx + 64 +
          2 * (nx * nx + nx * nu + nu * (nx + 1)) + nu * (nx + 1) + nx * nx + nu * nu + nx + 160 + (2 * MAX_T + 4) / 2;
 }
 
@@ -510,11 +510,6 @@ __device__ void load_kf(const Inst<NX, NU, F>& I, Smem<F>& S) {
 
 // ----------------------------------------------------------------------------
 // Task iteration helpers.
-struct EntryPos {
-  int c;    // cone (local)
-  int le;   // index inside the cone (0 = t slot)
-};
-
 __device__ __forceinline__ int next_task(int* ctr) {
   int t = 0;
   if (lane_id() == 0) t = atomicAdd(ctr, 1);
@@ -1232,7 +1227,7 @@ __device__ void fa_commit(const Inst<NX, NU, F>& I, Smem<F>& S) {
 // (du, p) block on wave 0.
 template <int NX, int NU>
 struct QPScratch {
-  L<double> *V, *v, *PA, *PB, *Huu, *Hux, *hu, *Lc, *tmp, *red;   // Lc: Cholesky factor of Huu
+  L<double> *V, *v, *PA, *PB, *Huu, *Hux, *hu, *tmp, *red;
   L<double>* AB;      // double buffer of one stage's data, halves of AB_N doubles: A (NX*NX),
                       // B (NX*NU), then x_k, u_k (backward pass); A and B only in the forward rollout
   static constexpr int AB_N = NX * NX + NX * NU + NU * (NX + 1);
@@ -1260,7 +1255,6 @@ __device__ QPScratch<NX, NU> qp_carve(L<double>* q, L<double>* gfb, L<double>* g
   s.Huu = q; q += NU * NU;
   s.Hux = q; q += NU * NX;
   s.hu = q; q += NU;
-  s.Lc = q; q += NU * NU;
   s.tmp = q; q += 2 * NX;
   s.red = q; q += 64;
   s.AB = q; q += 2 * QPScratch<NX, NU>::AB_N;
@@ -2255,7 +2249,6 @@ template <int NX, int NU, typename F, int METHOD>
 __device__ double kkt_residual(const Inst<NX, NU, F>& I, Smem<F>& S, const SolveOpts& o, double sig, bool pending,
                                int W) {
   const int T = I.T;
-  const double r = I.r;
   // accumulator of sum_j A_hat_j' zeta_j, [(k*NU + u)*NX + x].  In the FP64
   // form it takes the LDS of the adjoint accumulator Racc, whose contents (the
   // next K-solve's input) are saved to global scratch meanwhile and restored at
@@ -2537,7 +2530,6 @@ __device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, L<c
   Inst<NX, NU, F> I = make_inst<NX, NU, F>(g, ii);
   const int W = blockDim.x / NRTO_WAVE;
   Smem<F> S = carve<F>(smem, I.T, NX, NU, W);
-  const int T = I.T;
   double rho = (o.cont && prev.rho > 0.0) ? prev.rho : o.rho;
   // phase timers (device wall clock ticks, read by thread 0 after block barriers)
   const long long t_start = wall_clock64();
