@@ -257,6 +257,14 @@ struct Inst {
 // argument block on the stack inside loops: a stack reload is a vector-memory
 // load, and waiting for it also waits for every global load issued before it
 // (the prefetches of the next stage).
+// Value of lane l (wave-uniform l) of a double in every lane.
+__device__ __forceinline__ double lane_read(double v, int l) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, l);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 template <typename P>
 __device__ __forceinline__ P uni(P p) {
   if constexpr (sizeof(P) == 8) {
@@ -2118,7 +2126,8 @@ __device__ __noinline__ int qp_block(const Inst<NX, NU, F> Iarg, QPScratch<NX, N
 // instance view by value and made wave-uniform.
 template <int NX, int NU, typename F, int METHOD, typename AccP, typename KP>
 __device__ __noinline__ void kkt_entry_pass(const Inst<NX, NU, F> Iarg, AccP acc, KP kk, L<F>* bl_all, double sig,
-                                            double rho_fa, int pending_i) {
+                                            double rho_fa, int pending_i, int w0) {
+  if ((int)wave_id() < w0) return;   // waves below w0 take no task
   const Inst<NX, NU, F> I = uniform_inst(Iarg);
   const int T = I.T;
   const double r = I.r;
@@ -2151,7 +2160,7 @@ __device__ __noinline__ void kkt_entry_pass(const Inst<NX, NU, F> Iarg, AccP acc
       if (cz != 0.0) atomicAdd(&acc[(k * NU + u) * NX + x], cz);
     }
   };
-  for (int t = uni((int)wave_id()); t < I.ntask; t += W) {
+  for (int t = uni((int)wave_id()) - w0; t < I.ntask; t += W - w0) {
     const WaveTask tk = I.tasks[t];
     if (tk.ncone == 1 && tk.len > NRTO_WAVE) {
       const int c = tk.cone, len = tk.len, k0 = tk.k0;
@@ -2243,6 +2252,117 @@ __device__ __noinline__ void kkt_entry_pass(const Inst<NX, NU, F> Iarg, AccP acc
   }
 }
 
+// T1 of the KKT residual: the input-stationarity term, from three costate
+// recursions run backward over the horizon on one wave (lanes 0..NX-1 the cost
+// costate, NX..2NX-1 the constraint-multiplier costate, 2NX..3NX-1 the
+// trust-region costate).  The costates stay in registers and are read across
+// lanes; the cone loops issue their loads four cones at a time.  Every lane
+// returns the value.
+template <int NX, int NU, typename F>
+__device__ __noinline__ double kkt_t1(const Inst<NX, NU, F> Iarg) {
+  static_assert(3 * NX <= NRTO_WAVE, "three costates in one wave");
+  const Inst<NX, NU, F> I = uniform_inst(Iarg);
+  const int T = I.T;
+  const int lane = lane_id();
+  const int which = lane / NX, i = lane - which * NX;
+  const double mu = *I.mu;
+  double qrow[NX], xg[NX], ru[NU];
+#pragma unroll
+  for (int j = 0; j < NX; ++j) {
+    qrow[j] = I.Q[i * NX + j];
+    xg[j] = I.xg[j];
+  }
+#pragma unroll
+  for (int w = 0; w < NU; ++w) ru[w] = lane < NU ? I.Ru[lane * NU + w] : 0.0;
+  double lam = 0.0;
+  double g1m = 0.0, g2m = 0.0, g3m = 0.0, gsm = 0.0;
+  for (int t = T; t >= 1; --t) {
+    const int k = t - 1;
+    // the stage's loads first, so that they are in flight together: lane i's
+    // column of A_k, row lane of B_k' (lanes below NU) and u_k + du_k
+    double av[NX], bv[NX], ud[NU];
+    {
+      const double* A = I.A + (int64_t)k * NX * NX;
+      const double* B = I.B + (int64_t)k * NX * NU;
+      const int bl = lane < NU ? lane : 0;
+#pragma unroll
+      for (int j = 0; j < NX; ++j) {
+        av[j] = A[j * NX + i];
+        bv[j] = B[j * NU + bl];
+      }
+#pragma unroll
+      for (int w = 0; w < NU; ++w) ud[w] = I.uhat[k * NU + w] + I.du[k * NU + w];
+    }
+    // stage terms of time t
+    double add = 0.0;
+    if (which == 0) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < NX; ++j) s += qrow[j] * (I.xhat[t * NX + j] - xg[j] + I.dx[t * NX + j]);
+      add = 2.0 * s;
+    } else if (which == 1) {
+      const int c1 = I.tls[t + 1];
+      for (int c = I.tls[t]; c < c1; c += 4) {
+        double pv[4], wv[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const bool in = c + b < c1;
+          pv[b] = in ? I.C(CA_PI, c + b) : 0.0;
+          wv[b] = in ? I.W[(int64_t)(c + b) * NX + i] : 0.0;
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          if (c + b < c1) add += pv[b] * wv[b];
+      }
+    } else if (which == 2) {
+      add = mu * I.dx[t * NX + i];
+    }
+    lam += add;
+    // gradients at step k from lambda_{k+1}, and lambda_k = A_k' lambda_{k+1}
+    double g1 = 0.0, g2 = 0.0, g3 = 0.0;
+#pragma unroll
+    for (int w = 0; w < NU; ++w) g1 += ru[w] * ud[w];
+    g1 *= 2.0;
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < NX; ++j) {
+      const double l0 = lane_read(lam, j), l1 = lane_read(lam, NX + j), l2 = lane_read(lam, 2 * NX + j);
+      g1 += bv[j] * l0;
+      g2 += bv[j] * l1;
+      g3 += bv[j] * l2;
+      s += av[j] * (which == 0 ? l0 : (which == 1 ? l1 : l2));
+    }
+    if (lane < NU) {
+      const int c1 = I.tlc[k + 1];
+      for (int c = I.tlc[k]; c < c1; c += 4) {
+        double pv[4];
+        int ci[4], cs[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const bool in = c + b < c1;
+          const int32_t* m = I.cm + (int64_t)(in ? c + b : c) * CM_N;
+          ci[b] = in ? m[CM_CIDX] : -1;
+          cs[b] = m[CM_CSIGN];
+          pv[b] = in ? I.C(CA_PI, c + b) : 0.0;
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          if (ci[b] == lane) g2 += pv[b] * (double)cs[b];
+      }
+      g1m = fmax(g1m, fabs(g1));
+      g2m = fmax(g2m, fabs(g2));
+      g3m = fmax(g3m, fabs(g3));
+      gsm = fmax(gsm, fabs(g1 + g2 + g3));
+    }
+    lam = which < 3 ? s : 0.0;
+  }
+  g1m = wave_max(g1m);
+  g2m = wave_max(g2m);
+  g3m = wave_max(g3m);
+  gsm = wave_max(gsm);
+  return gsm / (1.0 + fmax(g1m, fmax(g2m, g3m)));
+}
+
 // FP64 KKT residual (see the oracle's definition).  Uses K (double), the
 // multipliers CA_PI, mu, and zeta from the method state.
 template <int NX, int NU, typename F, int METHOD>
@@ -2255,6 +2375,13 @@ __device__ double kkt_residual(const Inst<NX, NU, F>& I, Smem<F>& S, const Solve
   // the end, and K is read from the LDS of the gain copy Kf (idle from the
   // (du, p) block to the next K-solve); else the accumulator is global scratch
   // and K is read from global memory.
+  // With more than one wave, wave 0 runs the T1 recursion (which reads none of
+  // what the entry pass writes) while the other waves take the entry tasks.
+  const int w0 = W > 1 ? 1 : 0;
+  auto t1_wave0 = [&]() {
+    const double v = kkt_t1<NX, NU, F>(I);
+    if (lane_id() == 0) S.red[64] = v;
+  };
   if constexpr (sizeof(F) == 8) {
     L<double>* acc = (L<double>*)S.Racc;
     L<double>* kl = (L<double>*)S.Kf;
@@ -2264,12 +2391,15 @@ __device__ double kkt_residual(const Inst<NX, NU, F>& I, Smem<F>& S, const Solve
       kl[i] = I.K[i];
     }
     __syncthreads();
-    kkt_entry_pass<NX, NU, F, METHOD>(I, acc, (const L<double>*)kl, S.bl, sig, o.rho, pending ? 1 : 0);
+    if (w0 && wave_id() == 0) t1_wave0();
+    else kkt_entry_pass<NX, NU, F, METHOD>(I, acc, (const L<double>*)kl, S.bl, sig, o.rho, pending ? 1 : 0, w0);
   } else {
     for (int i = threadIdx.x; i < T * NU * NX; i += blockDim.x) I.kscr[i] = 0.0;
     __syncthreads();
-    kkt_entry_pass<NX, NU, F, METHOD>(I, I.kscr, (const G<double>*)I.K, S.bl, sig, o.rho, pending ? 1 : 0);
+    if (w0 && wave_id() == 0) t1_wave0();
+    else kkt_entry_pass<NX, NU, F, METHOD>(I, I.kscr, (const G<double>*)I.K, S.bl, sig, o.rho, pending ? 1 : 0, w0);
   }
+  if (!w0) t1_wave0();   // a single wave: after its entry tasks
   __syncthreads();
   // per-cone terms
   double mx[4] = {0.0, 0.0, 0.0, 0.0};   // T3 num, T5 num, T6 num, T7 num
@@ -2318,76 +2448,7 @@ __device__ double kkt_residual(const Inst<NX, NU, F>& I, Smem<F>& S, const Solve
   block_max<4>(S.red, nm, W);
   block_max<4>(S.red, nm2, W);
   block_max<4>(S.red, t2, W);
-  // T1 by costate recursions on wave 0
-  double t1v = 0.0;
-  if (wave_id() == 0) {
-    QPScratch<NX, NU> q = qp_carve<NX, NU>(S.qp, S.gfb, S.gff);
-    const int lane = lane_id();
-    // lanes 0..NX-1: cost costate; NX..2NX-1: pi costate; 2NX..3NX-1: trust costate
-    const int which = lane / NX, i = lane - which * NX;
-    double lam = 0.0;
-    const double mu = *I.mu;
-    double g1m = 0.0, g2m = 0.0, g3m = 0.0, gsm = 0.0;
-    double* lv = q.PA;   // 3*NX doubles
-    for (int t = T; t >= 1; --t) {
-      // add the stage terms of time t
-      if (which < 3) {
-        double add = 0.0;
-        if (which == 0) {
-          double s = 0.0;
-          for (int j = 0; j < NX; ++j) s += I.Q[i * NX + j] * (I.xhat[t * NX + j] - I.xg[j] + I.dx[t * NX + j]);
-          add = 2.0 * s;
-        } else if (which == 1) {
-          for (int c = I.tls[t]; c < I.tls[t + 1]; ++c) add += I.C(CA_PI, c) * I.W[(int64_t)c * NX + i];
-        } else {
-          add = mu * I.dx[t * NX + i];
-        }
-        lam += add;
-        lv[which * NX + i] = lam;
-      }
-      wave_sync();
-      const int k = t - 1;
-      const double* A = I.A + (int64_t)k * NX * NX;
-      const double* B = I.B + (int64_t)k * NX * NU;
-      // gradients at step k from lambda_{k+1} = lv
-      if (lane < NU) {
-        double g1 = 0.0, g2 = 0.0, g3 = 0.0;
-#pragma unroll
-        for (int w = 0; w < NU; ++w) g1 += I.Ru[lane * NU + w] * (I.uhat[k * NU + w] + I.du[k * NU + w]);
-        g1 *= 2.0;
-#pragma unroll
-        for (int j = 0; j < NX; ++j) {
-          g1 += B[j * NU + lane] * lv[j];
-          g2 += B[j * NU + lane] * lv[NX + j];
-          g3 += B[j * NU + lane] * lv[2 * NX + j];
-        }
-        for (int c = I.tlc[k]; c < I.tlc[k + 1]; ++c) {
-          const int32_t* m = I.cm + c * CM_N;
-          if (m[CM_CIDX] == lane) g2 += I.C(CA_PI, c) * (double)m[CM_CSIGN];
-        }
-        g1m = fmax(g1m, fabs(g1));
-        g2m = fmax(g2m, fabs(g2));
-        g3m = fmax(g3m, fabs(g3));
-        gsm = fmax(gsm, fabs(g1 + g2 + g3));
-      }
-      // lambda_k = A_k' lambda_{k+1}
-      if (which < 3) {
-        double s = 0.0;
-#pragma unroll
-        for (int j = 0; j < NX; ++j) s += A[j * NX + i] * lv[which * NX + j];
-        lam = s;
-      }
-      wave_sync();
-    }
-    g1m = wave_max(g1m);
-    g2m = wave_max(g2m);
-    g3m = wave_max(g3m);
-    gsm = wave_max(gsm);
-    t1v = gsm / (1.0 + fmax(g1m, fmax(g2m, g3m)));
-    if (lane_id() == 0) S.red[64] = t1v;
-  }
-  __syncthreads();
-  t1v = S.red[64];
+  const double t1v = S.red[64];
   const double rt = I.r_trust;
   const double psi = I.iscr[ISCR_PSI];
   const double mu = *I.mu;
