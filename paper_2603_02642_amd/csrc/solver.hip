@@ -1758,14 +1758,17 @@ __device__ __noinline__ void riccati(const Inst<NX, NU, F> Iarg, QPScratch<NX, N
 constexpr int CB = 4;
 
 // Set CA_ACT from the iterate (du, dx); returns the number of flags that changed.
+// The (du, p) block's cone scans and reductions are shared by the workgroup's
+// waves (every wave calls them; red: block-reduction slots).
 template <int NX, int NU, typename F>
-__device__ int set_active(const Inst<NX, NU, F>& I, const double* dx, const double* du) {
+__device__ int set_active(const Inst<NX, NU, F>& I, const double* dx, const double* du, double* red, int W) {
   int changed = 0;
-  for (int c0 = lane_id(); c0 < I.ng; c0 += CB * NRTO_WAVE) {
+  const int nt = (int)blockDim.x;
+  for (int c0 = (int)threadIdx.x; c0 < I.ng; c0 += CB * nt) {
     double f[CB], old[CB];
 #pragma unroll
     for (int i = 0; i < CB; ++i) {
-      const int c = c0 + i * NRTO_WAVE;
+      const int c = c0 + i * nt;
       f[i] = old[i] = 0.0;
       if (c < I.ng) {
         const double a = I.C(CA_BETA, c) + cons_lin<NX, NU, F>(I, c, dx, du);
@@ -1775,15 +1778,16 @@ __device__ int set_active(const Inst<NX, NU, F>& I, const double* dx, const doub
     }
 #pragma unroll
     for (int i = 0; i < CB; ++i) {
-      const int c = c0 + i * NRTO_WAVE;
+      const int c = c0 + i * nt;
       if (c < I.ng) {
         if (f[i] != old[i]) ++changed;
         I.C(CA_ACT, c) = f[i];
       }
     }
   }
-  wave_sync();
-  return (int)wave_sum((double)changed);
+  double v[1] = {(double)changed};
+  block_sum<1>(red, v, W);   // its barriers also publish CA_ACT to the workgroup
+  return (int)v[0];
 }
 
 // Exact line search along (du2 - du, dx2 - dx) for the squared-hinge objective.
@@ -1792,11 +1796,11 @@ __device__ int set_active(const Inst<NX, NU, F>& I, const double* dx, const doub
 // sweep) when 2 n_g doubles fit there, else in its per-cone columns; the
 // piecewise-linear derivative is then evaluated from there at every trial step.
 template <int NX, int NU, typename F>
-__device__ double line_search(const Inst<NX, NU, F>& I, const QPScratch<NX, NU>& q, double rho, double mu) {
-  const int lane = lane_id();
+__device__ double line_search(const Inst<NX, NU, F>& I, const QPScratch<NX, NU>& q, double rho, double mu, int W) {
+  const int tid = (int)threadIdx.x, nt = (int)blockDim.x;
   const int T = I.T;
   double dHd = 0.0, gd = 0.0;
-  for (int idx = lane; idx < T * NU; idx += NRTO_WAVE) {
+  for (int idx = tid; idx < T * NU; idx += nt) {
     const int k = idx / NU, u = idx - k * NU;
     double hd = 0.0, hg = 0.0;
 #pragma unroll
@@ -1809,7 +1813,7 @@ __device__ double line_search(const Inst<NX, NU, F>& I, const QPScratch<NX, NU>&
     dHd += 2.0 * hd * du_;
     gd += 2.0 * hg * du_;
   }
-  for (int idx = lane; idx < T * NX; idx += NRTO_WAVE) {
+  for (int idx = tid; idx < T * NX; idx += nt) {
     const int t = idx / NX + 1, i = idx - (t - 1) * NX;
     double hd = 0.0, hg = 0.0;
 #pragma unroll
@@ -1822,15 +1826,13 @@ __device__ double line_search(const Inst<NX, NU, F>& I, const QPScratch<NX, NU>&
     dHd += (2.0 * hd + mu * di) * di;
     gd += (2.0 * hg + mu * I.dx[t * NX + i]) * di;
   }
-  dHd = wave_sum(dHd);
-  gd = wave_sum(gd);
   const bool in_lds = 2 * I.ng <= T * NU * NX;
   L<double>* lae = q.gfb;   // [2c]: a, [2c + 1]: e
-  for (int c0 = lane; c0 < I.ng; c0 += CB * NRTO_WAVE) {
+  for (int c0 = tid; c0 < I.ng; c0 += CB * nt) {
     double av[CB], ev[CB];
 #pragma unroll
     for (int i = 0; i < CB; ++i) {
-      const int c = c0 + i * NRTO_WAVE;
+      const int c = c0 + i * nt;
       av[i] = ev[i] = 0.0;
       if (c < I.ng) {
         const double a0 = cons_lin<NX, NU, F>(I, c, I.dx, I.du);
@@ -1841,7 +1843,7 @@ __device__ double line_search(const Inst<NX, NU, F>& I, const QPScratch<NX, NU>&
     }
 #pragma unroll
     for (int i = 0; i < CB; ++i) {
-      const int c = c0 + i * NRTO_WAVE;
+      const int c = c0 + i * nt;
       if (c >= I.ng) continue;
       if (in_lds) {
         lae[2 * c] = av[i];
@@ -1852,11 +1854,16 @@ __device__ double line_search(const Inst<NX, NU, F>& I, const QPScratch<NX, NU>&
       }
     }
   }
-  wave_sync();
+  {
+    double v[2] = {dHd, gd};
+    block_sum<2>(q.red, v, W);   // its barriers also publish (a, e)
+    dHd = v[0];
+    gd = v[1];
+  }
   if (dHd <= 0.0) return 0.0;
   auto deriv = [&](double s, double& slope) {
     double f = 0.0, sl = 0.0;
-    for (int c = lane; c < I.ng; c += NRTO_WAVE) {
+    for (int c = tid; c < I.ng; c += nt) {
       double a, e;
       if (in_lds) {
         a = lae[2 * c];
@@ -1871,8 +1878,10 @@ __device__ double line_search(const Inst<NX, NU, F>& I, const QPScratch<NX, NU>&
         sl += e * e;
       }
     }
-    f = wave_sum(f);
-    sl = wave_sum(sl);
+    double v[2] = {f, sl};
+    block_sum<2>(q.red, v, W);
+    f = v[0];
+    sl = v[1];
     slope = dHd + rho * sl;
     return s * dHd + gd + rho * f;
   };
@@ -1915,47 +1924,54 @@ __device__ double line_search(const Inst<NX, NU, F>& I, const QPScratch<NX, NU>&
   return s;
 }
 
-// Semismooth Newton at fixed mu from the current iterate (du, dx).
+// Semismooth Newton at fixed mu from the current iterate (du, dx).  Every wave
+// of the workgroup runs it: the Riccati sweep on wave 0, the cone scans, the
+// line search and the iterate updates on all waves, with every decision taken
+// from block reductions (so block-uniform).
 template <int NX, int NU, typename F>
-__device__ int ssn(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double rho, double mu) {
+__device__ int ssn(const Inst<NX, NU, F>& I, QPScratch<NX, NU>& q, double rho, double mu, int W) {
   const int T = I.T;
-  const int lane = lane_id();
-  set_active<NX, NU, F>(I, I.dx, I.du);
+  const int tid = (int)threadIdx.x, nt = (int)blockDim.x;
+  set_active<NX, NU, F>(I, I.dx, I.du, q.red, W);
   int solves = 0;
   for (int it = 0; it < 60; ++it) {
-    riccati<NX, NU, F>(I, q, rho, mu);
+    if (wave_id() == 0) riccati<NX, NU, F>(I, q, rho, mu);
+    __syncthreads();   // the candidate (du2, dx2) and the gains to every wave
     ++solves;
     // does the candidate keep the active set?
     int changed = 0;
-    for (int c0 = lane; c0 < I.ng; c0 += CB * NRTO_WAVE) {
+    for (int c0 = tid; c0 < I.ng; c0 += CB * nt) {
 #pragma unroll
       for (int i = 0; i < CB; ++i) {
-        const int c = c0 + i * NRTO_WAVE;
+        const int c = c0 + i * nt;
         if (c < I.ng) {
           const double a = I.C(CA_BETA, c) + cons_lin<NX, NU, F>(I, c, I.dx2, I.du2);
           if ((a > 0.0 ? 1.0 : 0.0) != I.C(CA_ACT, c)) ++changed;
         }
       }
     }
-    changed = (int)wave_sum((double)changed);
+    {
+      double v[1] = {(double)changed};
+      block_sum<1>(q.red, v, W);
+      changed = (int)v[0];
+    }
     if (changed == 0) {
-      for (int i = lane; i < T * NU; i += NRTO_WAVE) I.du[i] = I.du2[i];
-      for (int i = lane; i < (T + 1) * NX; i += NRTO_WAVE) I.dx[i] = I.dx2[i];
-      wave_sync();
+      for (int i = tid; i < T * NU; i += nt) I.du[i] = I.du2[i];
+      for (int i = tid; i < (T + 1) * NX; i += nt) I.dx[i] = I.dx2[i];
+      __syncthreads();
       break;
     }
-    const double s = line_search<NX, NU, F>(I, q, rho, mu);
-    double step = 0.0;
-    for (int i = lane; i < T * NU; i += NRTO_WAVE) {
+    const double s = line_search<NX, NU, F>(I, q, rho, mu, W);
+    double step[1] = {0.0};
+    for (int i = tid; i < T * NU; i += nt) {
       const double d = s * (I.du2[i] - I.du[i]);
-      step = fmax(step, fabs(d));
+      step[0] = fmax(step[0], fabs(d));
       I.du[i] += d;
     }
-    for (int i = lane; i < (T + 1) * NX; i += NRTO_WAVE) I.dx[i] += s * (I.dx2[i] - I.dx[i]);
-    wave_sync();
-    step = wave_max(step);
-    set_active<NX, NU, F>(I, I.dx, I.du);
-    if (step == 0.0) break;
+    for (int i = tid; i < (T + 1) * NX; i += nt) I.dx[i] += s * (I.dx2[i] - I.dx[i]);
+    block_max<1>(q.red, step, W);   // its barriers also publish (du, dx)
+    set_active<NX, NU, F>(I, I.dx, I.du, q.red, W);
+    if (step[0] == 0.0) break;
   }
   return solves;
 }
@@ -1965,6 +1981,15 @@ __device__ double state_norm(const Inst<NX, NU, F>& I) {
   double s = 0.0;
   for (int i = lane_id(); i < (I.T + 1) * NX; i += NRTO_WAVE) s += I.dx[i] * I.dx[i];
   return sqrt(wave_sum(s));
+}
+
+// ||dx|| over the workgroup's waves (block-uniform).
+template <int NX, int NU, typename F>
+__device__ double state_norm_block(const Inst<NX, NU, F>& I, double* red, int W) {
+  double v[1] = {0.0};
+  for (int i = (int)threadIdx.x; i < (I.T + 1) * NX; i += (int)blockDim.x) v[0] += I.dx[i] * I.dx[i];
+  block_sum<1>(red, v, W);
+  return sqrt(v[0]);
 }
 
 // Full (du, p) block: returns Riccati solves used.  Requires CA_BETA = g0 + c.
@@ -2004,16 +2029,18 @@ __device__ __noinline__ int qp_block(const Inst<NX, NU, F> Iarg, QPScratch<NX, N
   // upper end is known the multiplier grows by at most 16x per step.
   const double r = I.r_trust;
   const double tol = 1e-13 * r;
+  const int W = (int)(blockDim.x / NRTO_WAVE);
   int solves = 0;
-  {
+  if (wave_id() == 0) {
     L<int>* tl = (L<int>*)q.tl;
     for (int i = lane_id(); i < 2 * I.T + 3; i += NRTO_WAVE) tl[i] = I.tls[i];   // tls then tlc
     wave_sync();
+    rollout_dx<NX, NU, F>(I);
   }
-  rollout_dx<NX, NU, F>(I);
+  __syncthreads();
   auto eval = [&](double m) {
-    solves += ssn<NX, NU, F>(I, q, rho, m);
-    return state_norm<NX, NU, F>(I);
+    solves += ssn<NX, NU, F>(I, q, rho, m, W);
+    return state_norm_block<NX, NU, F>(I, q.red, W);
   };
   // start: when the last block ended with an inactive trust region (mu = 0, also
   // at a cold start), mu = 0 first -- a single evaluation whenever the region
@@ -2107,12 +2134,12 @@ __device__ __noinline__ int qp_block(const Inst<NX, NU, F> Iarg, QPScratch<NX, N
     }
   }
   (void)have_lo;
-  if (lane_id() == 0) {
+  if (threadIdx.x == 0) {
     *I.mu = mu;
     I.iscr[ISCR_PSI] = psi;
     if (mu > 0.0) I.iscr[ISCR_MUHINT] = mu;
   }
-  wave_sync();
+  __syncthreads();
   return solves;
 }
 
@@ -2691,19 +2718,16 @@ __device__ void solve_instance(const DevPtrs& g, const SolveOpts& o, int ii, L<c
       t_dr += now - t_mark;
       t_mark = now;
     }
-    // (du, p) block on wave 0
-    if (wave_id() == 0) {
+    // (du, p) block: Riccati sweeps on wave 0, cone scans on every wave
+    {
       QPScratch<NX, NU> q = qp_carve<NX, NU>(S.qp, S.gfb, S.gff);
-      const int n = qp_block<NX, NU, F>(I, q, rho);
-      if (lane_id() == 0) S.red[65] = (double)n;
+      qpn += qp_block<NX, NU, F>(I, q, rho);
     }
-    __syncthreads();
     {
       const long long now = wall_clock64();
       t_qp += now - t_mark;
       t_mark = now;
     }
-    qpn += (int)S.red[65];
     // p, pi from the (du, p) solution; then the FullADMM k_v step; dual updates
     double acc2[3] = {0.0, 0.0, 0.0};
     for (int c = threadIdx.x; c < I.ng; c += blockDim.x) {
