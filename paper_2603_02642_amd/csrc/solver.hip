@@ -314,6 +314,30 @@ struct Buf {
     return *(const T*)((const char*)p + voff + soff);
 #endif
   }
+  // elements at byte offsets voff + soff and voff + soff + 8 (one 16-byte load)
+  __device__ void ld2(uint32_t voff, uint32_t soff, T& v0, T& v1) const {
+#if defined(__HIP_DEVICE_COMPILE__)
+    static_assert(sizeof(T) == 8, "64-bit elements");
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    const auto w = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+    v0 = __builtin_bit_cast(T, (u32x2){w[0], w[1]});
+    v1 = __builtin_bit_cast(T, (u32x2){w[2], w[3]});
+#else
+    v0 = *(const T*)((const char*)p + voff + soff);
+    v1 = *(const T*)((const char*)p + voff + soff + 8);
+#endif
+  }
+  // store v at byte offset voff + soff; an offset past the n elements stores
+  // nothing (the buffer's range check), so lanes can opt out without a branch
+  __device__ void st(uint32_t voff, uint32_t soff, T v) const {
+#if defined(__HIP_DEVICE_COMPILE__)
+    static_assert(sizeof(T) == 8, "64-bit elements");
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+#else
+    *(T*)((char*)p + voff + soff) = v;
+#endif
+  }
 };
 
 // The instance view with every member made wave-uniform (see uni).
@@ -1414,23 +1438,6 @@ struct StagePrefetch {
   }
 };
 
-// Stage data of the forward rollout: A_k and B_k, staged one stage ahead.
-template <int NX, int NU>
-struct FwdPrefetch {
-  static constexpr int NA = NX * NX, NB = NX * NU;
-  LanePrefetch<NA> a;
-  LanePrefetch<NB> b;
-  // stage k of the arrays A and B
-  __device__ void load(const Buf<double>& bA, const Buf<double>& bB, int k) {
-    a.load(bA, k * NA);
-    b.load(bB, k * NB);
-  }
-  __device__ void store(double* dst) const {
-    a.store(dst);
-    b.store(dst + NA);
-  }
-};
-
 // Riccati solve of the LQ problem of the current active set at multiplier mu;
 // result in (du2, dx2).  Compiled out of line (one copy, its own register
 // allocation) with the instance view and LDS carve-up by value.
@@ -1708,47 +1715,64 @@ __device__ __noinline__ void riccati(const Inst<NX, NU, F> Iarg, QPScratch<NX, N
       wave_sync();
     }
   }
-  // forward rollout from dx_0 = 0: the stage's A, B are staged in LDS one stage
-  // ahead, the gains are read from LDS; the current state and control stay in
-  // LDS (q.tmp), their global copies are only written
-  FwdPrefetch<NX, NU> fp;
-  auto fwd_load = [&](int k) { fp.load(bA, bB, k); };
-  if (lane < NX) {
-    q.tmp[lane] = 0.0;
-    I.dx2[lane] = 0.0;
-  }
-  fwd_load(0);
-  fp.store(q.ab(0));
-  wave_sync();
-  for (int k = 0; k < T; ++k) {
-    const double* A = q.ab(k);
-    const double* B = A + NX * NX;
-    if (k + 1 < T) fwd_load(k + 1);
-    if (lane < NU) {
-      const double* gx = q.gfb + (k * NU + lane) * NX;
-      double s = q.gff[k * NU + lane];
+  // forward rollout from dx_0 = 0, u_k = G_k x_k + g_k, x_{k+1} = A_k x_k + B_k u_k.
+  // The state (lanes 0..NX-1) and the control (lanes 0..NU-1) stay in registers
+  // and are read across lanes; lane i < NX holds row i of A_k and B_k in
+  // registers, loaded FD stages ahead (register sets picked at compile time: the
+  // stage loop is unrolled by FD); the gains are read from LDS.  Loads and the
+  // stores of (du2, dx2) are issued without branches (lanes without a row or an
+  // element use an offset past the end, which the buffer's range check turns
+  // into a zero load or a dropped store; stages past T-1 reload stage T-1), so
+  // that the compiler's wait counts keep FD stages in flight.
+  constexpr int FD = 4;
+  constexpr uint32_t OOR = 0x7FFFFFF0u;   // byte offset past any array here
+  const Buf<double> bdu2 = Buf<double>::make(I.du2, (int64_t)T * NU);
+  const Buf<double> bdx2 = Buf<double>::make(I.dx2, (int64_t)(T + 1) * NX);
+  const uint32_t vra = lane < NX ? (uint32_t)(lane * NX) * 8u : OOR;
+  const uint32_t vrb = lane < NX ? (uint32_t)(lane * NU) * 8u : OOR;
+  double ar[FD][NX], br[FD][NU];
+  auto row_load = [&](double (&a)[NX], double (&b)[NU], int k) {   // 16-byte loads
+    const int kk = k < T ? k : T - 1;
+    const uint32_t sa = (uint32_t)(kk * NX * NX) * 8u, sb = (uint32_t)(kk * NX * NU) * 8u;
 #pragma unroll
-      for (int j = 0; j < NX; ++j) s += gx[j] * q.tmp[j];
-      q.tmp[NX + lane] = s;
-      I.du2[k * NU + lane] = s;
-    }
-    wave_sync();
-    double xn = 0.0;
-    if (lane < NX) {
-      double s = 0.0;
+    for (int j = 0; j + 1 < NX; j += 2) bA.ld2(vra + (uint32_t)j * 8u, sa, a[j], a[j + 1]);
+    if constexpr (NX % 2) a[NX - 1] = bA.ld(vra + (uint32_t)(NX - 1) * 8u, sa);
 #pragma unroll
-      for (int j = 0; j < NX; ++j) s += A[lane * NX + j] * q.tmp[j];
+    for (int u = 0; u + 1 < NU; u += 2) bB.ld2(vrb + (uint32_t)u * 8u, sb, b[u], b[u + 1]);
+    if constexpr (NU % 2) b[NU - 1] = bB.ld(vrb + (uint32_t)(NU - 1) * 8u, sb);
+  };
 #pragma unroll
-      for (int u = 0; u < NU; ++u) s += B[lane * NU + u] * q.tmp[NX + u];
-      xn = s;
+  for (int d = 0; d < FD; ++d) row_load(ar[d], br[d], d);
+  bdx2.st(lane < NX ? (uint32_t)lane * 8u : OOR, 0u, 0.0);
+  // nothing outstanding when the loop starts (vmcnt 0): the compiler's counts at
+  // the loop head are then those of the loop's own loads, FD stages deep
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+  const int ul = lane < NU ? lane : 0;
+  double xr = 0.0;
+  for (int k0 = 0; k0 < T; k0 += FD) {
+#pragma unroll
+    for (int d = 0; d < FD; ++d) {
+      const int k = k0 + d;
+      // the sweep's end leaves the function: a path that left only the unrolled
+      // body would reach the loop head with other loads outstanding, and the
+      // compiler's wait counts there would drain the prefetch every FD stages
+      if (k >= T) return;
+      const L<double>* gx = q.gfb + (k * NU + ul) * NX;
+      double us = q.gff[k * NU + ul];
+      double xn = 0.0;
+#pragma unroll
+      for (int j = 0; j < NX; ++j) {
+        const double xj = lane_read(xr, j);
+        us += gx[j] * xj;
+        xn += ar[d][j] * xj;
+      }
+      bdu2.st(lane < NU ? (uint32_t)(k * NU + lane) * 8u : OOR, 0u, us);
+#pragma unroll
+      for (int u = 0; u < NU; ++u) xn += br[d][u] * lane_read(us, u);
+      bdx2.st(lane < NX ? (uint32_t)((k + 1) * NX + lane) * 8u : OOR, 0u, xn);
+      xr = xn;
+      row_load(ar[d], br[d], k + FD);
     }
-    wave_sync();
-    if (lane < NX) {
-      q.tmp[lane] = xn;
-      I.dx2[(k + 1) * NX + lane] = xn;
-    }
-    if (k + 1 < T) fp.store(q.ab(k + 1));
-    wave_sync();
   }
 }
 
