@@ -1276,8 +1276,8 @@ __device__ void fa_commit(const Inst<NX, NU, F>& I, Smem<F>& S) {
 template <int NX, int NU>
 struct QPScratch {
   L<double> *V, *v, *PA, *PB, *Huu, *Hux, *hu, *tmp, *red;
-  L<double>* AB;      // double buffer of one stage's data, halves of AB_N doubles: A (NX*NX),
-                      // B (NX*NU), then x_k, u_k (backward pass); A and B only in the forward rollout
+  L<double>* AB;      // double buffer of one stage's data for the backward pass, halves of
+                      // AB_N doubles: A (NX*NX), B (NX*NU), then x_k, u_k
   static constexpr int AB_N = NX * NX + NX * NU + NU * (NX + 1);
   // half (k & 1) of the double buffer (address arithmetic: an array of two
   // pointers indexed at run time would live on the stack)
